@@ -1,0 +1,86 @@
+/*
+ * oracle7d.h -- FP64 reference of the 7DGS render path (test infrastructure).
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * use this library.  It shares nothing with the HIP library.
+ *
+ * Array layouts (structure of arrays, n = number of Gaussians):
+ *   inputs (FP64):  mu_p[3][n], mu_t[n], mu_d[3][n], L[28][n] (entry (i,j),
+ *                   i >= j, at plane i*(i+1)/2+j; dims x,y,z,t,dx,dy,dz),
+ *                   alpha[n], sh[48][n] (plane 3k+ch)
+ *   outputs (FP64): mu_c[3][n], cov_c[6][n] (xx,xy,xz,yy,yz,zz), alpha_c[n],
+ *                   mean2d[2][n], conic[3][n] (a,b,c with
+ *                   q = a dx^2 + 2 b dx dy + c dy^2), depth[n], rgb[3][n],
+ *                   rect[4][n] (tile x0, y0, x1, y1; x1, y1 exclusive)
+ *   images:         image[3][h][w], final_T[h][w], ncontrib[h][w]
+ */
+#ifndef ORACLE7D_H
+#define ORACLE7D_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* A view exactly as the scene generator stores it (FP32). */
+typedef struct {
+    float R[9];        /* world -> camera rotation, row-major (rows: right, down, forward) */
+    float c[3];        /* camera centre, world */
+    float fx, fy, cx, cy;
+    int32_t W, H;
+    float t;           /* observed time */
+    float d[3];        /* view direction the Gaussians are conditioned on */
+    float lambda_t, lambda_d;
+    float bg[3];
+} ora_view;
+
+/* Decision bands for flagging pixels whose FP32 result may legitimately
+ * differ from FP64 (see the parity protocol). */
+typedef struct {
+    double tau_alpha;   /* relative band around ALPHA_MIN */
+    double tau_T;       /* relative band around T_MIN */
+    double tau_z;       /* relative depth gap treated as a tie */
+    double impact_min;  /* ignore events whose colour impact is below this */
+} ora_flagcfg;
+
+#define ORA_FLAG_ALPHA 1u
+#define ORA_FLAG_T 2u
+#define ORA_FLAG_DEPTH 4u
+
+/* Returns the number of Gaussians with a non-positive L diagonal or a
+ * non-SPD block; status[g] (optional) holds 1 (diagonal) | 2 (not SPD). */
+int ora_slice(int64_t n, const double* mu_p, const double* mu_t, const double* mu_d,
+              const double* L, const double* alpha, const ora_view* v,
+              double* mu_c, double* cov_c, double* alpha_c, double* f_temp, double* f_dir,
+              int32_t* status);
+
+/* Returns the number of visible Gaussians. */
+int64_t ora_project(int64_t n, const double* mu_c, const double* cov_c, const double* alpha_c,
+                    const double* sh, const ora_view* v, double* mean2d, double* conic,
+                    double* depth, double* rgb, int32_t* rect, uint8_t* visible);
+
+/* Visible Gaussians ordered by (depth ascending, index ascending). */
+int64_t ora_order(int64_t n, const double* depth, const uint8_t* visible, int64_t* order);
+
+/* Brute-force compositing of the crop [x0, x0+w) x [y0, y0+h). */
+int ora_composite(int64_t n, const double* mean2d, const double* conic, const double* alpha_c,
+                  const double* depth, const double* rgb, int64_t m, const int64_t* order,
+                  const ora_view* v, int x0, int y0, int w, int h, const ora_flagcfg* fc,
+                  double* image, double* final_T, int32_t* ncontrib, uint64_t* chash,
+                  uint32_t* flags);
+
+/* slice + project + order + composite. */
+int ora_render(int64_t n, const double* mu_p, const double* mu_t, const double* mu_d,
+               const double* L, const double* alpha, const double* sh, const ora_view* v,
+               int x0, int y0, int w, int h, const ora_flagcfg* fc,
+               double* image, double* final_T, int32_t* ncontrib, uint64_t* chash,
+               uint32_t* flags);
+
+void ora_sh_basis(double x, double y, double z, double* Y);
+int ora_num_threads(void);
+void ora_set_num_threads(int nt);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
