@@ -1,0 +1,260 @@
+/*
+ * sd7.h -- C ABI of lib7dgs.so, the MI355X (gfx950) render path of 7D
+ * Gaussian Splatting (7DGS).
+ *
+ * The path (Sec. 4.2 and Sec. 4.4 of the paper):
+ *   sd7_slice        condition every 7D Gaussian (position, time, direction)
+ *                    on the observed time t and view direction d: conditional
+ *                    mean (eq. cond_mean), covariance (eq. cond_cov) and
+ *                    opacity alpha_cond = alpha f_temp f_dir (eq. temp_mod,
+ *                    eq. dir_mod); Algorithm 1 steps 3-6, with the adaptive
+ *                    refinement of steps 1-2 taken as the identity ("w/o AGR").
+ *   sd7_project      standard perspective (EWA) projection of each conditional
+ *                    3D Gaussian to a 2D Gaussian, culling, footprint, depth,
+ *                    and the degree-3 SH colour (Sec. 3, eq. 2; Sec. 4.1).
+ *   sd7_bin          depth sort of the kept Gaussians, per-tile lists of
+ *                    (tile, Gaussian) pairs in (depth, index) order.
+ *   sd7_rasterize    depth-aware, opacity-blended front-to-back compositing
+ *                    of each 16x16 pixel tile (Sec. 4.4).
+ *   sd7_rasterize_backward, sd7_project_backward, sd7_slice_backward
+ *                    the reverse pass of the three compute stages
+ *                    (differentiable rasterization, Sec. 4.4).
+ *
+ * Constants the paper leaves open, fixed here: tiles of 16x16 pixels;
+ * alpha = min(0.99, alpha_cond exp(-q/2)); a Gaussian is skipped at a pixel
+ * when alpha < 1/255 (FP32 value); compositing stops before the Gaussian
+ * that would bring transmittance below 1e-4; near plane z = 0.2; 0.3 px^2
+ * added to the 2D covariance diagonal; the EWA Jacobian is evaluated at
+ * view-ray ratios clamped to 1.3x the half field of view; depth is the
+ * camera-space z; ties go to the smaller Gaussian index; colour =
+ * max(0, 0.5 + SH(dir)) with dir the unit vector from the camera centre to
+ * the conditional mean (world space); pixel (i, j) has centre (i+0.5, j+0.5).
+ *
+ * BATCHES.  Every entry point takes an array of nf frames (1 <= nf <=
+ * SD7_MAX_FRAMES).  A frame is one (scene, view) render request; frames of
+ * one call may use different scenes and resolutions.  All frames of a call
+ * are processed by the same kernel launches; no frame's result depends on
+ * the others (a frame renders bit-identically alone and in any batch), except
+ * that the pair arena is shared: frames that do not fit are flagged
+ * SD7_FLAG_PAIR_OVERFLOW and render as background.
+ *
+ * MEMORY.  The caller owns all memory.  Scene arrays, frame outputs and the
+ * workspace are device pointers; frame descriptors are host memory, read
+ * during the call only.  The library never allocates or frees device memory.
+ * All intermediate arrays live in one caller-allocated workspace whose size
+ * and layout sd7_plan() computes from the frames and a pair capacity; the
+ * layout is part of this ABI (see sd7_layout) so callers may inspect every
+ * intermediate.  The same (frames, nf, workspace) must be passed to all stage
+ * calls of one render, in order: slice, project, bin, rasterize, then (for
+ * training) rasterize_backward, project_backward, slice_backward.
+ *
+ * ASYNCHRONY.  Calls enqueue work on the given HIP stream (NULL = the null
+ * stream) and return without waiting, except where stated.  Host-side
+ * argument errors return synchronously and enqueue nothing.
+ *
+ * ERRORS.  Every call returns SD7_OK (0) or a negative sd7_status;
+ * sd7_last_error() gives a message (per host thread).  Conditions found on
+ * the device go to the per-frame flags word in the workspace (sd7_layout.
+ * off_counts, word SD7_CNT_FLAGS of each frame).  No exception or abort
+ * crosses the ABI.
+ *
+ * THREADS.  A context may be used from several host threads on different
+ * streams with disjoint workspaces.
+ */
+#ifndef SD7_H
+#define SD7_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sd7_status;
+#define SD7_OK 0
+#define SD7_EINVAL (-1)     /* bad argument (null pointer, size out of range, ...) */
+#define SD7_EHIP (-2)       /* a HIP runtime call failed */
+#define SD7_EWORKSPACE (-3) /* workspace smaller than sd7_plan() requires */
+#define SD7_ENOMEM (-4)     /* host allocation failed */
+
+#define SD7_MAX_FRAMES 64
+#define SD7_TILE 16
+#define SD7_MAX_DIM 16384
+
+/* per-frame device flags (bitmask) */
+#define SD7_FLAG_NONPOS_DIAG 1u   /* some L has a diagonal entry <= 0 (Gaussian culled) */
+#define SD7_FLAG_NONFINITE 2u     /* a non-finite conditional statistic (Gaussian culled) */
+#define SD7_FLAG_PAIR_OVERFLOW 4u /* the pair arena was too small: frame not rasterized */
+
+/* per-frame device counters: SD7_CNT_WORDS uint32 words per frame */
+#define SD7_CNT_KEPT 0      /* Gaussians that survive culling */
+#define SD7_CNT_PAIRS 1     /* (tile, Gaussian) pairs of the frame */
+#define SD7_CNT_PAIR_BASE 2 /* first arena slot of the frame's pairs */
+#define SD7_CNT_FLAGS 3     /* SD7_FLAG_* bits */
+#define SD7_CNT_WORDS 16
+
+typedef struct sd7_ctx sd7_ctx;
+typedef void* sd7_stream; /* a hipStream_t */
+
+/* A scene of n 7D Gaussians (Sec. 4.1), device memory, FP32 structure of
+ * arrays, read only:
+ *   mu_p [3][n]  spatial mean          mu_t [n]      temporal mean
+ *   mu_d [3][n]  directional mean      alpha [n]     opacity in (0, 1)
+ *   L   [28][n]  Cholesky factor of the 7x7 covariance Sigma = L L^T, lower
+ *                triangle packed row-major: entry (i, j), i >= j, in plane
+ *                i*(i+1)/2 + j; dimension order (x, y, z, t, dx, dy, dz).
+ *                Diagonal entries must be positive (the caller's activation).
+ *   sh  [48][n]  SH coefficients, plane 3*k + channel, k = l*l + l + m. */
+typedef struct {
+    const float* mu_p;
+    const float* mu_t;
+    const float* mu_d;
+    const float* L;
+    const float* alpha;
+    const float* sh;
+    int64_t n;
+} sd7_scene;
+
+/* A pinhole view at time t (host memory, by value).  R_wc is the row-major
+ * world-to-camera rotation (camera axes x right, y down, z forward); c the
+ * camera centre; (fx, fy, cx, cy) the intrinsics in pixels; d the view
+ * direction the Gaussians are conditioned on; bg the background colour. */
+typedef struct {
+    float R_wc[9];
+    float c[3];
+    float fx, fy, cx, cy;
+    int32_t W, H;
+    float t;
+    float d[3];
+    float lambda_t, lambda_d;
+    float bg[3];
+} sd7_view;
+
+/* Gradient outputs of one frame (device, overwritten by the backward):
+ * same shapes as the scene arrays; alpha is the activated opacity. */
+typedef struct {
+    float* mu_p;
+    float* mu_t;
+    float* mu_d;
+    float* L;
+    float* alpha;
+    float* sh;
+} sd7_scene_grad;
+
+/* One render request. */
+typedef struct {
+    sd7_scene scene;
+    sd7_view view;
+    float* image;            /* out [3][H][W]: C + T_final * bg */
+    float* final_T;          /* out [H][W]: transmittance after compositing */
+    uint32_t* last;          /* out [H][W]: tile-list entries up to the last contributor */
+    const float* dL_dimage;  /* in  [3][H][W]: backward only (may be NULL otherwise) */
+    sd7_scene_grad grad;     /* out: backward only (may be NULL otherwise) */
+} sd7_frame;
+
+/* Workspace layout.  Every offset is in bytes from the workspace base and a
+ * multiple of 256.  Per-Gaussian arrays hold the frames back to back: frame f
+ * owns Gaussians [g0[f], g0[f] + n_f) with g0 the running sum of n; a
+ * k-plane array stores frame f's planes at element k_planes*g0[f] + k*n_f.
+ *   off_counts   uint32 [nf][SD7_CNT_WORDS]    per-frame counters and flags
+ *   off_mu_c     float  [3 planes]             conditional mean
+ *   off_cov_c    float  [6 planes]             conditional covariance (xx,xy,xz,yy,yz,zz)
+ *   off_alpha_c  float  [1 plane]              conditional opacity
+ *   off_splat    float  [Ntot][12]             per Gaussian: u, v, conic a, b, c,
+ *                                              opacity, r, g, b, depth, 0, 0 (AoS)
+ *   off_rect     uint32 [Ntot][2]              tile box: (x0 | y0 << 16, x1 | y1 << 16), x1, y1 exclusive
+ *   off_depth_key uint32 [Ntot]                float bits of depth; 0xFFFFFFFF = culled
+ *   off_order    uint32 [Ntot]                 frame-local indices of kept Gaussians in
+ *                                              (depth, index) order; entries >= kept unused
+ *   off_pair_tile, off_pair_g  uint32 [capacity]  sorted pairs: tile id (frame-local,
+ *                                              ty*tiles_x+tx) and frame-local Gaussian index;
+ *                                              frame f at arena slot counts[f][SD7_CNT_PAIR_BASE]
+ *   off_ranges   uint32 [Ttot][2]              per tile [begin, end) arena slots; frame f's
+ *                                              tiles start at the running sum of its tile counts
+ *   off_d_splat  float  [9 planes]             backward: dL/d(u, v, a, b, c, opacity, r, g, b)
+ *   off_d_mu_c, off_d_cov_c, off_d_alpha_c     backward: dL/d of the slice outputs
+ */
+typedef struct {
+    size_t bytes;
+    int32_t nframes;
+    int32_t tile_sort_passes;
+    int64_t n_total;
+    int64_t tiles_total;
+    int64_t pair_capacity;
+    size_t off_table;
+    size_t off_counts;
+    size_t off_mu_c, off_cov_c, off_alpha_c;
+    size_t off_splat, off_rect, off_depth_key;
+    size_t off_order;
+    size_t off_pair_tile, off_pair_g;
+    size_t off_ranges;
+    size_t off_d_splat, off_d_mu_c, off_d_cov_c, off_d_alpha_c;
+    size_t off_scratch; /* sort and scan temporaries; no stable meaning */
+    int64_t g0[SD7_MAX_FRAMES];
+    int64_t tile0[SD7_MAX_FRAMES];
+} sd7_layout;
+
+/* Context on HIP device `device`.  *out is set on success. */
+sd7_status sd7_create(int device, sd7_ctx** out);
+void sd7_destroy(sd7_ctx* ctx);
+
+/* Message of the last failing call on this host thread ("" if none). */
+const char* sd7_last_error(void);
+
+/* Host only.  Workspace size and layout for these frames and a pair arena of
+ * `pair_capacity` (tile, Gaussian) pairs shared by all frames (each frame's
+ * share is rounded up to a multiple of 4096 pairs).  Checks the frames:
+ * 1 <= nf <= SD7_MAX_FRAMES, 0 <= n < 2^31, 1 <= W, H <= SD7_MAX_DIM, total
+ * Gaussians and tiles < 2^31, pair_capacity < 2^31, non-null scene arrays
+ * when n > 0, non-null image/final_T/last.  Returns SD7_EINVAL otherwise. */
+sd7_status sd7_plan(const sd7_frame* frames, int nf, int64_t pair_capacity, sd7_layout* out);
+
+/* Stage calls.  `ws`/`ws_bytes`: the workspace (device); `pair_capacity` must
+ * equal the value given to sd7_plan.  SD7_EWORKSPACE if ws_bytes is too small. */
+
+/* Sec. 4.2: writes mu_c, cov_c, alpha_c; zeroes the counters. */
+sd7_status sd7_slice(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t pair_capacity,
+                     void* ws, size_t ws_bytes, sd7_stream stream);
+/* Sec. 4.4 projection: writes splat, rect, depth_key and the KEPT counters. */
+sd7_status sd7_project(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t pair_capacity,
+                       void* ws, size_t ws_bytes, sd7_stream stream);
+/* Depth sort, pair emission, tile sort, tile ranges: writes order, pair_tile,
+ * pair_g, ranges and the PAIRS / PAIR_BASE counters; sets
+ * SD7_FLAG_PAIR_OVERFLOW for frames whose pairs do not fit. */
+sd7_status sd7_bin(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t pair_capacity,
+                   void* ws, size_t ws_bytes, sd7_stream stream);
+/* Front-to-back compositing into each frame's image, final_T and last. */
+sd7_status sd7_rasterize(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t pair_capacity,
+                         void* ws, size_t ws_bytes, sd7_stream stream);
+/* slice + project + bin + rasterize in one call. */
+sd7_status sd7_render(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t pair_capacity,
+                      void* ws, size_t ws_bytes, sd7_stream stream);
+
+/* Reverse of the compositing (front-to-back recomputation; no per-pixel
+ * list state is stored): reads each frame's dL_dimage, image, final_T, last
+ * and the bins; writes d_splat (zeroed first, then accumulated). */
+sd7_status sd7_rasterize_backward(sd7_ctx* ctx, const sd7_frame* frames, int nf,
+                                  int64_t pair_capacity, void* ws, size_t ws_bytes,
+                                  sd7_stream stream);
+/* Reverse of the projection and SH colour: reads d_splat, writes d_mu_c,
+ * d_cov_c, d_alpha_c and each frame's grad.sh. */
+sd7_status sd7_project_backward(sd7_ctx* ctx, const sd7_frame* frames, int nf,
+                                int64_t pair_capacity, void* ws, size_t ws_bytes,
+                                sd7_stream stream);
+/* Reverse of the slice (FP64 inside): reads d_mu_c, d_cov_c, d_alpha_c and
+ * writes each frame's grad.mu_p, mu_t, mu_d, L, alpha.  Frames of one call
+ * must not share gradient buffers. */
+sd7_status sd7_slice_backward(sd7_ctx* ctx, const sd7_frame* frames, int nf,
+                              int64_t pair_capacity, void* ws, size_t ws_bytes,
+                              sd7_stream stream);
+
+/* Blocks until the stream is idle and copies the nf x SD7_CNT_WORDS counters
+ * to host memory `out`. */
+sd7_status sd7_read_counts(sd7_ctx* ctx, int nf, const void* ws, uint32_t* out,
+                           sd7_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SD7_H */

@@ -1,0 +1,104 @@
+"""ctypes binding of lib7dgs.so (include/sd7.h).  Argument marshalling only:
+every step of the render path runs in the HIP library.  There is no CPU
+fallback: loading fails loudly when the library has not been built."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "lib7dgs.so")
+
+SD7_OK, SD7_EINVAL, SD7_EHIP, SD7_EWORKSPACE, SD7_ENOMEM = 0, -1, -2, -3, -4
+SD7_MAX_FRAMES = 64
+SD7_TILE = 16
+SD7_FLAG_NONPOS_DIAG, SD7_FLAG_NONFINITE, SD7_FLAG_PAIR_OVERFLOW = 1, 2, 4
+SD7_CNT_KEPT, SD7_CNT_PAIRS, SD7_CNT_PAIR_BASE, SD7_CNT_FLAGS = 0, 1, 2, 3
+SD7_CNT_NEEDED = 4          # pairs the frame needed (internal word, also set on overflow)
+SD7_CNT_WORDS = 16
+
+P = ctypes.c_void_p
+f32 = ctypes.c_float
+
+
+class Sd7Scene(ctypes.Structure):
+    _fields_ = [("mu_p", P), ("mu_t", P), ("mu_d", P), ("L", P), ("alpha", P), ("sh", P),
+                ("n", ctypes.c_int64)]
+
+
+class Sd7View(ctypes.Structure):
+    _fields_ = [("R_wc", f32 * 9), ("c", f32 * 3), ("fx", f32), ("fy", f32), ("cx", f32),
+                ("cy", f32), ("W", ctypes.c_int32), ("H", ctypes.c_int32), ("t", f32),
+                ("d", f32 * 3), ("lambda_t", f32), ("lambda_d", f32), ("bg", f32 * 3)]
+
+
+class Sd7SceneGrad(ctypes.Structure):
+    _fields_ = [("mu_p", P), ("mu_t", P), ("mu_d", P), ("L", P), ("alpha", P), ("sh", P)]
+
+
+class Sd7Frame(ctypes.Structure):
+    _fields_ = [("scene", Sd7Scene), ("view", Sd7View), ("image", P), ("final_T", P),
+                ("last", P), ("dL_dimage", P), ("grad", Sd7SceneGrad)]
+
+
+_OFFS = ["off_table", "off_counts", "off_mu_c", "off_cov_c", "off_alpha_c", "off_splat",
+         "off_rect", "off_depth_key", "off_order", "off_pair_tile", "off_pair_g", "off_ranges",
+         "off_d_splat", "off_d_mu_c", "off_d_cov_c", "off_d_alpha_c", "off_scratch"]
+
+
+class Sd7Layout(ctypes.Structure):
+    _fields_ = ([("bytes", ctypes.c_size_t), ("nframes", ctypes.c_int32),
+                 ("tile_sort_passes", ctypes.c_int32), ("n_total", ctypes.c_int64),
+                 ("tiles_total", ctypes.c_int64), ("pair_capacity", ctypes.c_int64)]
+                + [(k, ctypes.c_size_t) for k in _OFFS]
+                + [("g0", ctypes.c_int64 * SD7_MAX_FRAMES),
+                   ("tile0", ctypes.c_int64 * SD7_MAX_FRAMES)])
+
+
+STAGES = ("sd7_slice", "sd7_project", "sd7_bin", "sd7_rasterize", "sd7_render",
+          "sd7_rasterize_backward", "sd7_project_backward", "sd7_slice_backward")
+EXPORTS = ("sd7_create", "sd7_destroy", "sd7_last_error", "sd7_plan", "sd7_read_counts") + STAGES
+
+
+class Sd7Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (once).  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"lib7dgs.so not built at {path}; run __graft_entry__.build() "
+                           "(the render path has no CPU fallback)")
+    L = ctypes.CDLL(path)
+    L.sd7_create.argtypes = [ctypes.c_int, ctypes.POINTER(P)]
+    L.sd7_create.restype = ctypes.c_int32
+    L.sd7_destroy.argtypes = [P]
+    L.sd7_destroy.restype = None
+    L.sd7_last_error.argtypes = []
+    L.sd7_last_error.restype = ctypes.c_char_p
+    L.sd7_plan.argtypes = [ctypes.POINTER(Sd7Frame), ctypes.c_int, ctypes.c_int64,
+                           ctypes.POINTER(Sd7Layout)]
+    L.sd7_plan.restype = ctypes.c_int32
+    for name in STAGES:
+        fn = getattr(L, name)
+        fn.argtypes = [P, ctypes.POINTER(Sd7Frame), ctypes.c_int, ctypes.c_int64, P,
+                       ctypes.c_size_t, P]
+        fn.restype = ctypes.c_int32
+    L.sd7_read_counts.argtypes = [P, ctypes.c_int, P, ctypes.POINTER(ctypes.c_uint32), P]
+    L.sd7_read_counts.restype = ctypes.c_int32
+    _lib = L
+    return L
+
+
+def check(code: int):
+    if code != SD7_OK:
+        msg = load().sd7_last_error().decode(errors="replace")
+        raise Sd7Error(code, msg)

@@ -1,0 +1,523 @@
+// Host side of lib7dgs: argument checks, workspace planning, frame tables and
+// kernel launches behind the C ABI of include/sd7.h.  Built as one
+// translation unit with the kernel files.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "common.h"
+#include "slice.hip"
+#include "project.hip"
+#include "bin.hip"
+#include "raster.hip"
+
+using namespace sd7;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+sd7_status fail(sd7_status code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) return fail(SD7_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define LAUNCH_CHECK(name)                                                               \
+    do {                                                                                 \
+        hipError_t e_ = hipGetLastError();                                               \
+        if (e_ != hipSuccess) return fail(SD7_EHIP, "launch %s: %s", name, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kRing = 64;             // pinned staging slots for frame tables
+constexpr int kPersistentBlocks = 2048;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+// Offsets of the scratch sub-arrays (inside off_scratch .. bytes).
+struct Scratch {
+    size_t sk_a, sv_a, sk_b;         // depth sort ping-pong (keys a, vals a, keys b)
+    size_t pt_b, pg_b;               // pair ping-pong buffers
+    size_t toff;                     // tile offsets (scan of tiles per sorted Gaussian)
+    size_t segs_all, segs_kept, segs_pairs;
+    size_t tot_all, tot_kept, tot_pairs;
+    size_t hist, partials, words;
+};
+
+struct Plan {
+    sd7_layout L;
+    Scratch S;
+    uint32_t max_wt_depth, max_wt_pairs;
+    size_t hist_entries, partial_entries;
+    BlockMap gmap;   // blocks of 256 Gaussians per frame
+    BlockMap tmap;   // one block per tile
+    uint32_t gblocks, tblocks;
+};
+
+sd7_status make_plan(const sd7_frame* fr, int nf, int64_t cap, Plan& P, bool need_bwd)
+{
+    if (!fr) return fail(SD7_EINVAL, "frames is NULL");
+    if (nf < 1 || nf > SD7_MAX_FRAMES) return fail(SD7_EINVAL, "nf=%d outside [1, %d]", nf, SD7_MAX_FRAMES);
+    if (cap < 0 || cap >= (int64_t)1 << 31) return fail(SD7_EINVAL, "pair_capacity=%lld outside [0, 2^31)", (long long)cap);
+    std::memset(&P, 0, sizeof(P));
+    sd7_layout& L = P.L;
+    L.nframes = nf;
+    L.pair_capacity = cap;
+    int64_t ntot = 0, ttot = 0;
+    uint32_t max_tiles = 1;
+    uint64_t wt_depth = 0;
+    P.gmap.nf = nf;
+    P.tmap.nf = nf;
+    for (int f = 0; f < nf; ++f) {
+        const sd7_frame& F = fr[f];
+        const int64_t n = F.scene.n;
+        if (n < 0 || n >= (int64_t)1 << 31) return fail(SD7_EINVAL, "frame %d: n=%lld outside [0, 2^31)", f, (long long)n);
+        if (n > 0 && (!F.scene.mu_p || !F.scene.mu_t || !F.scene.mu_d || !F.scene.L || !F.scene.alpha || !F.scene.sh))
+            return fail(SD7_EINVAL, "frame %d: NULL scene array", f);
+        const int W = F.view.W, H = F.view.H;
+        if (W < 1 || H < 1 || W > SD7_MAX_DIM || H > SD7_MAX_DIM)
+            return fail(SD7_EINVAL, "frame %d: W=%d H=%d outside [1, %d]", f, W, H, SD7_MAX_DIM);
+        if (!F.image || !F.final_T || !F.last) return fail(SD7_EINVAL, "frame %d: NULL image/final_T/last", f);
+        if (!(F.view.fx > 0.f) || !(F.view.fy > 0.f)) return fail(SD7_EINVAL, "frame %d: focal length must be > 0", f);
+        if (need_bwd && (!F.dL_dimage || !F.grad.mu_p || !F.grad.mu_t || !F.grad.mu_d || !F.grad.L ||
+                         !F.grad.alpha || !F.grad.sh))
+            return fail(SD7_EINVAL, "frame %d: NULL dL_dimage or gradient array", f);
+        const uint32_t tx = ceil_div(W, kTile), ty = ceil_div(H, kTile);
+        L.g0[f] = ntot;
+        L.tile0[f] = ttot;
+        P.gmap.start[f] = P.gblocks;
+        P.tmap.start[f] = P.tblocks;
+        P.gblocks += ceil_div(n, kBlock);
+        P.tblocks += tx * ty;
+        ntot += n;
+        ttot += (int64_t)tx * ty;
+        max_tiles = std::max(max_tiles, tx * ty);
+        wt_depth += ceil_div(n, kSortItems);
+    }
+    P.gmap.start[nf] = P.gblocks;
+    P.tmap.start[nf] = P.tblocks;
+    if (ntot >= (int64_t)1 << 31) return fail(SD7_EINVAL, "total Gaussians %lld >= 2^31", (long long)ntot);
+    if (ttot >= (int64_t)1 << 31) return fail(SD7_EINVAL, "total tiles %lld >= 2^31", (long long)ttot);
+    if (cap + (int64_t)nf * kSortItems >= (int64_t)1 << 31) return fail(SD7_EINVAL, "pair capacity too large");
+    L.n_total = ntot;
+    L.tiles_total = ttot;
+    int bits = 0;
+    while ((1u << bits) < max_tiles) ++bits;
+    L.tile_sort_passes = std::max(1, (bits + 7) / 8);
+    P.max_wt_depth = (uint32_t)wt_depth;
+    P.max_wt_pairs = ceil_div(cap, kSortItems) + nf;
+
+    const size_t N = (size_t)ntot, T = (size_t)ttot, C = (size_t)cap;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t o = off; off = align_up(off + bytes); return o; };
+    L.off_table = take(sizeof(FrameDev) * nf);
+    L.off_counts = take(sizeof(uint32_t) * SD7_CNT_WORDS * nf);
+    L.off_mu_c = take(4 * 3 * N);
+    L.off_cov_c = take(4 * 6 * N);
+    L.off_alpha_c = take(4 * N);
+    L.off_splat = take(4 * kSplatFloats * N);
+    L.off_rect = take(8 * N);
+    L.off_depth_key = take(4 * N);
+    L.off_order = take(4 * N);
+    L.off_pair_tile = take(4 * C);
+    L.off_pair_g = take(4 * C);
+    L.off_ranges = take(8 * T);
+    L.off_d_splat = take(4 * 9 * N);
+    L.off_d_mu_c = take(4 * 3 * N);
+    L.off_d_cov_c = take(4 * 6 * N);
+    L.off_d_alpha_c = take(4 * N);
+    L.off_scratch = off;
+    Scratch& S = P.S;
+    S.sk_a = take(4 * N);
+    S.sv_a = take(4 * N);
+    S.sk_b = take(4 * N);
+    S.pt_b = take(4 * C);
+    S.pg_b = take(4 * C);
+    S.toff = take(4 * (N + 16));
+    S.segs_all = take(sizeof(SortSeg) * nf);
+    S.segs_kept = take(sizeof(SortSeg) * nf);
+    S.segs_pairs = take(sizeof(SortSeg) * nf);
+    S.tot_all = take(sizeof(SortTotals));
+    S.tot_kept = take(sizeof(SortTotals));
+    S.tot_pairs = take(sizeof(SortTotals));
+    P.hist_entries = 256 * (size_t)std::max(P.max_wt_depth, P.max_wt_pairs);
+    S.hist = take(4 * P.hist_entries);
+    P.partial_entries = std::max(P.hist_entries, N) / kScanItems + 4;
+    S.partials = take(4 * P.partial_entries);
+    S.words = take(4 * 64);
+    L.bytes = off;
+    return SD7_OK;
+}
+
+}  // namespace
+
+struct sd7_ctx {
+    int device = 0;
+    char* ring = nullptr;        // pinned host staging for frame tables
+    size_t slot_bytes = 0;
+    hipEvent_t ev[kRing];
+    bool used[kRing];
+    int next = 0;
+    std::mutex mu;
+};
+
+namespace {
+
+// Frame table -> workspace (through a pinned staging slot, stream ordered).
+sd7_status upload_table(sd7_ctx* ctx, const sd7_frame* fr, int nf, const Plan& P, char* ws, hipStream_t st)
+{
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    const int slot = ctx->next;
+    ctx->next = (ctx->next + 1) % kRing;
+    if (ctx->used[slot]) HIP_TRY(hipEventSynchronize(ctx->ev[slot]));
+    FrameDev* tab = reinterpret_cast<FrameDev*>(ctx->ring + (size_t)slot * ctx->slot_bytes);
+    for (int f = 0; f < nf; ++f) {
+        const sd7_frame& F = fr[f];
+        FrameDev& D = tab[f];
+        std::memset(&D, 0, sizeof(D));
+        D.mu_p = F.scene.mu_p; D.mu_t = F.scene.mu_t; D.mu_d = F.scene.mu_d;
+        D.L = F.scene.L; D.alpha = F.scene.alpha; D.sh = F.scene.sh;
+        D.image = F.image; D.final_T = F.final_T; D.last = F.last; D.dL_dimage = F.dL_dimage;
+        D.g_mu_p = F.grad.mu_p; D.g_mu_t = F.grad.mu_t; D.g_mu_d = F.grad.mu_d;
+        D.g_L = F.grad.L; D.g_alpha = F.grad.alpha; D.g_sh = F.grad.sh;
+        D.n = (uint32_t)F.scene.n;
+        D.g0 = (uint32_t)P.L.g0[f];
+        D.W = (uint32_t)F.view.W;
+        D.H = (uint32_t)F.view.H;
+        D.tiles_x = ceil_div(D.W, kTile);
+        D.tiles_y = ceil_div(D.H, kTile);
+        D.t0 = (uint32_t)P.L.tile0[f];
+        std::memcpy(D.R, F.view.R_wc, sizeof(D.R));
+        std::memcpy(D.c, F.view.c, sizeof(D.c));
+        D.fx = F.view.fx; D.fy = F.view.fy; D.cx = F.view.cx; D.cy = F.view.cy;
+        D.t = F.view.t;
+        std::memcpy(D.d, F.view.d, sizeof(D.d));
+        D.lambda_t = F.view.lambda_t; D.lambda_d = F.view.lambda_d;
+        std::memcpy(D.bg, F.view.bg, sizeof(D.bg));
+    }
+    HIP_TRY(hipMemcpyAsync(ws + P.L.off_table, tab, sizeof(FrameDev) * nf, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(ctx->ev[slot], st));
+    ctx->used[slot] = true;
+    return SD7_OK;
+}
+
+struct Call {
+    Plan P;
+    char* ws;
+    hipStream_t st;
+    const FrameDev* tab;
+    uint32_t* counts;
+    template <class T>
+    T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+sd7_status begin(sd7_ctx* ctx, const sd7_frame* fr, int nf, int64_t cap, void* ws, size_t ws_bytes,
+                 sd7_stream stream, Call& c, bool need_bwd)
+{
+    g_err[0] = 0;
+    if (!ctx) return fail(SD7_EINVAL, "ctx is NULL");
+    if (!ws) return fail(SD7_EINVAL, "workspace is NULL");
+    sd7_status s = make_plan(fr, nf, cap, c.P, need_bwd);
+    if (s != SD7_OK) return s;
+    if (ws_bytes < c.P.L.bytes)
+        return fail(SD7_EWORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, c.P.L.bytes);
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(SD7_EINVAL, "workspace not 256-byte aligned");
+    HIP_TRY(hipSetDevice(ctx->device));
+    c.ws = static_cast<char*>(ws);
+    c.st = static_cast<hipStream_t>(stream);
+    c.tab = c.at<FrameDev>(c.P.L.off_table);
+    c.counts = c.at<uint32_t>(c.P.L.off_counts);
+    return upload_table(ctx, fr, nf, c.P, c.ws, c.st);
+}
+
+sd7_status fill(const Call& c, void* p, size_t count, uint32_t value)
+{
+    if (count == 0) return SD7_OK;
+    const uint32_t blocks = std::min<uint32_t>(ceil_div(count, 256), 4096);
+    k_fill_u32<<<blocks, 256, 0, c.st>>>(static_cast<uint32_t*>(p), count, value);
+    LAUNCH_CHECK("k_fill_u32");
+    return SD7_OK;
+}
+
+// Exclusive scan in place; the length is host-known (len_dev null) or read on
+// the device.  The grand total lands in partials[ntiles] and *total_out.
+sd7_status scan(const Call& c, uint32_t* data, uint32_t len_host, const uint32_t* len_dev, uint32_t max_len,
+                uint32_t* total_out)
+{
+    uint32_t* part = c.at<uint32_t>(c.P.S.partials);
+    const uint32_t blocks = std::max(1u, std::min<uint32_t>(ceil_div(max_len, kScanItems), kPersistentBlocks));
+    k_scan_reduce<<<blocks, 256, 0, c.st>>>(data, len_host, len_dev, part);
+    LAUNCH_CHECK("k_scan_reduce");
+    k_scan_spine<<<1, 1024, 0, c.st>>>(part, len_host, len_dev, total_out);
+    LAUNCH_CHECK("k_scan_spine");
+    k_scan_down<<<blocks, 256, 0, c.st>>>(data, data, len_host, len_dev, part);
+    LAUNCH_CHECK("k_scan_down");
+    return SD7_OK;
+}
+
+sd7_status radix_pass(const Call& c, bool first, const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
+                      uint32_t* vout, const SortSeg* segs, const SortTotals* tot, uint32_t max_wt, int shift)
+{
+    if (max_wt == 0) return SD7_OK;
+    uint32_t* hist = c.at<uint32_t>(c.P.S.hist);
+    const int nf = c.P.L.nframes;
+    const uint32_t blocks = std::min<uint32_t>(max_wt, kPersistentBlocks);
+    if (first) k_radix_hist<true><<<blocks, 256, 0, c.st>>>(kin, segs, nf, tot, shift, hist);
+    else k_radix_hist<false><<<blocks, 256, 0, c.st>>>(kin, segs, nf, tot, shift, hist);
+    LAUNCH_CHECK("k_radix_hist");
+    sd7_status s = scan(c, hist, 0, &tot->hist_len, 256u * max_wt, nullptr);
+    if (s != SD7_OK) return s;
+    if (first) k_radix_scatter<true><<<blocks, 256, 0, c.st>>>(kin, vin, kout, vout, segs, nf, tot, shift, hist);
+    else k_radix_scatter<false><<<blocks, 256, 0, c.st>>>(kin, vin, kout, vout, segs, nf, tot, shift, hist);
+    LAUNCH_CHECK("k_radix_scatter");
+    return SD7_OK;
+}
+
+sd7_status do_slice(const Call& c)
+{
+    const sd7_layout& L = c.P.L;
+    sd7_status s = fill(c, c.counts, (size_t)SD7_CNT_WORDS * L.nframes, 0);
+    if (s != SD7_OK || c.P.gblocks == 0) return s;
+    k_slice<<<c.P.gblocks, kBlock, 0, c.st>>>(c.tab, c.P.gmap, c.at<float>(L.off_mu_c), c.at<float>(L.off_cov_c),
+                                               c.at<float>(L.off_alpha_c), c.counts);
+    LAUNCH_CHECK("k_slice");
+    return SD7_OK;
+}
+
+sd7_status do_project(const Call& c)
+{
+    const sd7_layout& L = c.P.L;
+    if (c.P.gblocks == 0) return SD7_OK;
+    k_project<<<c.P.gblocks, kBlock, 0, c.st>>>(c.tab, c.P.gmap, c.at<float>(L.off_mu_c), c.at<float>(L.off_cov_c),
+                                                 c.at<float>(L.off_alpha_c), c.at<float4>(L.off_splat),
+                                                 c.at<uint2>(L.off_rect), c.at<uint32_t>(L.off_depth_key), c.counts);
+    LAUNCH_CHECK("k_project");
+    return SD7_OK;
+}
+
+sd7_status do_bin(const Call& c)
+{
+    const sd7_layout& L = c.P.L;
+    const Scratch& S = c.P.S;
+    const int nf = L.nframes;
+    sd7_status s;
+    SortSeg* segs_all = c.at<SortSeg>(S.segs_all);
+    SortSeg* segs_kept = c.at<SortSeg>(S.segs_kept);
+    SortSeg* segs_pairs = c.at<SortSeg>(S.segs_pairs);
+    SortTotals* tot_all = c.at<SortTotals>(S.tot_all);
+    SortTotals* tot_kept = c.at<SortTotals>(S.tot_kept);
+    SortTotals* tot_pairs = c.at<SortTotals>(S.tot_pairs);
+    uint32_t* words = c.at<uint32_t>(S.words);
+    k_setup_depth<<<1, 64, 0, c.st>>>(c.tab, nf, c.counts, segs_all, tot_all, segs_kept, tot_kept);
+    LAUNCH_CHECK("k_setup_depth");
+    // depth sort: key_depth -> (a) -> (b) -> (a) -> (b = order)
+    uint32_t* ka = c.at<uint32_t>(S.sk_a);
+    uint32_t* va = c.at<uint32_t>(S.sv_a);
+    uint32_t* kb = c.at<uint32_t>(S.sk_b);
+    uint32_t* order = c.at<uint32_t>(L.off_order);
+    const uint32_t* dkey = c.at<uint32_t>(L.off_depth_key);
+    const uint32_t mw = c.P.max_wt_depth;
+    if ((s = radix_pass(c, true, dkey, nullptr, ka, va, segs_all, tot_all, mw, 0)) != SD7_OK) return s;
+    if ((s = radix_pass(c, false, ka, va, kb, order, segs_kept, tot_kept, mw, 8)) != SD7_OK) return s;
+    if ((s = radix_pass(c, false, kb, order, ka, va, segs_kept, tot_kept, mw, 16)) != SD7_OK) return s;
+    if ((s = radix_pass(c, false, ka, va, kb, order, segs_kept, tot_kept, mw, 24)) != SD7_OK) return s;
+    // tiles per sorted Gaussian -> exclusive offsets
+    uint32_t* toff = c.at<uint32_t>(S.toff);
+    if (c.P.gblocks) {
+        k_gather_ntiles<<<c.P.gblocks, kBlock, 0, c.st>>>(c.tab, c.P.gmap, c.counts, order,
+                                                          c.at<uint2>(L.off_rect), toff);
+        LAUNCH_CHECK("k_gather_ntiles");
+    }
+    const uint32_t ntot = (uint32_t)L.n_total;
+    if ((s = fill(c, words, 1, 0)) != SD7_OK) return s;
+    if (ntot && (s = scan(c, toff, ntot, nullptr, ntot, words)) != SD7_OK) return s;
+    k_setup_pairs<<<1, 64, 0, c.st>>>(c.tab, nf, ntot, toff, words, (uint32_t)L.pair_capacity, c.counts,
+                                      segs_pairs, tot_pairs);
+    LAUNCH_CHECK("k_setup_pairs");
+    if ((s = fill(c, c.at<uint32_t>(L.off_ranges), 2 * (size_t)L.tiles_total, 0)) != SD7_OK) return s;
+    // emit so that the last tile-sort pass lands in the pair_tile/pair_g arrays
+    uint32_t* pt_a = c.at<uint32_t>(L.off_pair_tile);
+    uint32_t* pg_a = c.at<uint32_t>(L.off_pair_g);
+    uint32_t* pt_b = c.at<uint32_t>(S.pt_b);
+    uint32_t* pg_b = c.at<uint32_t>(S.pg_b);
+    const int passes = L.tile_sort_passes;
+    uint32_t *ct = (passes & 1) ? pt_b : pt_a, *cg = (passes & 1) ? pg_b : pg_a;
+    uint32_t *ot = (passes & 1) ? pt_a : pt_b, *og = (passes & 1) ? pg_a : pg_b;
+    const uint32_t mwp = c.P.max_wt_pairs;
+    if (L.pair_capacity > 0) {
+        const uint32_t blocks = std::min<uint32_t>(mwp, kPersistentBlocks);
+        k_emit<<<blocks, 256, 0, c.st>>>(c.tab, c.counts, order, c.at<uint2>(L.off_rect), toff, segs_pairs, nf,
+                                         tot_pairs, ct, cg);
+        LAUNCH_CHECK("k_emit");
+        for (int p = 0; p < passes; ++p) {
+            if ((s = radix_pass(c, false, ct, cg, ot, og, segs_pairs, tot_pairs, mwp, 8 * p)) != SD7_OK) return s;
+            std::swap(ct, ot);
+            std::swap(cg, og);
+        }
+        k_ranges<<<blocks, 256, 0, c.st>>>(c.tab, pt_a, segs_pairs, nf, tot_pairs, c.at<uint2>(L.off_ranges));
+        LAUNCH_CHECK("k_ranges");
+    }
+    return SD7_OK;
+}
+
+sd7_status do_raster(const Call& c)
+{
+    const sd7_layout& L = c.P.L;
+    k_raster<<<c.P.tblocks, 256, 0, c.st>>>(c.tab, c.P.tmap, c.at<uint2>(L.off_ranges), c.at<uint32_t>(L.off_pair_g),
+                                             c.at<float4>(L.off_splat));
+    LAUNCH_CHECK("k_raster");
+    return SD7_OK;
+}
+
+sd7_status do_raster_bwd(const Call& c)
+{
+    const sd7_layout& L = c.P.L;
+    sd7_status s = fill(c, c.at<uint32_t>(L.off_d_splat), 9 * (size_t)L.n_total, 0);
+    if (s != SD7_OK) return s;
+    k_raster_bwd<<<c.P.tblocks, 256, 0, c.st>>>(c.tab, c.P.tmap, c.at<uint2>(L.off_ranges),
+                                                 c.at<uint32_t>(L.off_pair_g), c.at<float4>(L.off_splat),
+                                                 c.at<float>(L.off_d_splat));
+    LAUNCH_CHECK("k_raster_bwd");
+    return SD7_OK;
+}
+
+sd7_status do_project_bwd(const Call& c)
+{
+    const sd7_layout& L = c.P.L;
+    if (c.P.gblocks == 0) return SD7_OK;
+    k_project_bwd<<<c.P.gblocks, kBlock, 0, c.st>>>(c.tab, c.P.gmap, c.at<float>(L.off_mu_c), c.at<float>(L.off_cov_c),
+                                                     c.at<float>(L.off_alpha_c), c.at<uint32_t>(L.off_depth_key),
+                                                     c.at<float>(L.off_d_splat), c.at<float>(L.off_d_mu_c),
+                                                     c.at<float>(L.off_d_cov_c), c.at<float>(L.off_d_alpha_c));
+    LAUNCH_CHECK("k_project_bwd");
+    return SD7_OK;
+}
+
+sd7_status do_slice_bwd(const Call& c, const sd7_frame* frames, int nf)
+{
+    const sd7_layout& L = c.P.L;
+    if (c.P.gblocks == 0) return SD7_OK;
+    for (int a = 0; a < nf; ++a)
+        for (int b = a + 1; b < nf; ++b)
+            if (frames[a].scene.n > 0 && frames[a].grad.L == frames[b].grad.L)
+                return fail(SD7_EINVAL, "frames %d and %d share gradient buffers", a, b);
+    k_slice_bwd<<<c.P.gblocks, kBlock, 0, c.st>>>(c.tab, c.P.gmap, c.at<float>(L.off_d_mu_c),
+                                                   c.at<float>(L.off_d_cov_c), c.at<float>(L.off_d_alpha_c));
+    LAUNCH_CHECK("k_slice_bwd");
+    return SD7_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sd7_last_error(void) { return g_err; }
+
+sd7_status sd7_create(int device, sd7_ctx** out)
+{
+    g_err[0] = 0;
+    if (!out) return fail(SD7_EINVAL, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    HIP_TRY(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return fail(SD7_EINVAL, "device %d outside [0, %d)", device, count);
+    HIP_TRY(hipSetDevice(device));
+    sd7_ctx* c = new (std::nothrow) sd7_ctx();
+    if (!c) return fail(SD7_ENOMEM, "out of host memory");
+    c->device = device;
+    c->slot_bytes = align_up(sizeof(FrameDev) * SD7_MAX_FRAMES);
+    hipError_t e = hipHostMalloc((void**)&c->ring, c->slot_bytes * kRing, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(SD7_EHIP, "hipHostMalloc: %s", hipGetErrorString(e));
+    }
+    for (int i = 0; i < kRing; ++i) {
+        c->used[i] = false;
+        e = hipEventCreateWithFlags(&c->ev[i], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            for (int j = 0; j < i; ++j) (void)hipEventDestroy(c->ev[j]);
+            (void)hipHostFree(c->ring);
+            delete c;
+            return fail(SD7_EHIP, "hipEventCreate: %s", hipGetErrorString(e));
+        }
+    }
+    *out = c;
+    return SD7_OK;
+}
+
+void sd7_destroy(sd7_ctx* ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    for (int i = 0; i < kRing; ++i) {
+        if (ctx->used[i]) (void)hipEventSynchronize(ctx->ev[i]);
+        (void)hipEventDestroy(ctx->ev[i]);
+    }
+    (void)hipHostFree(ctx->ring);
+    delete ctx;
+}
+
+sd7_status sd7_plan(const sd7_frame* frames, int nf, int64_t pair_capacity, sd7_layout* out)
+{
+    g_err[0] = 0;
+    if (!out) return fail(SD7_EINVAL, "out is NULL");
+    Plan P;
+    sd7_status s = make_plan(frames, nf, pair_capacity, P, false);
+    if (s == SD7_OK) *out = P.L;
+    return s;
+}
+
+#define STAGE(name, bwd, ...)                                                                        \
+    sd7_status name(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t cap, void* ws, size_t ws_bytes, \
+                    sd7_stream stream)                                                                \
+    {                                                                                                 \
+        Call c;                                                                                       \
+        sd7_status s = begin(ctx, frames, nf, cap, ws, ws_bytes, stream, c, bwd);                     \
+        if (s != SD7_OK) return s;                                                                    \
+        __VA_ARGS__                                                                                   \
+    }
+
+STAGE(sd7_slice, false, { return do_slice(c); })
+STAGE(sd7_project, false, { return do_project(c); })
+STAGE(sd7_bin, false, { return do_bin(c); })
+STAGE(sd7_rasterize, false, { return do_raster(c); })
+STAGE(sd7_render, false, {
+    if ((s = do_slice(c)) != SD7_OK) return s;
+    if ((s = do_project(c)) != SD7_OK) return s;
+    if ((s = do_bin(c)) != SD7_OK) return s;
+    return do_raster(c);
+})
+STAGE(sd7_rasterize_backward, true, { return do_raster_bwd(c); })
+STAGE(sd7_project_backward, true, { return do_project_bwd(c); })
+STAGE(sd7_slice_backward, true, { return do_slice_bwd(c, frames, nf); })
+
+sd7_status sd7_read_counts(sd7_ctx* ctx, int nf, const void* ws, uint32_t* out, sd7_stream stream)
+{
+    g_err[0] = 0;
+    if (!ctx || !ws || !out) return fail(SD7_EINVAL, "NULL argument");
+    if (nf < 1 || nf > SD7_MAX_FRAMES) return fail(SD7_EINVAL, "nf=%d outside [1, %d]", nf, SD7_MAX_FRAMES);
+    HIP_TRY(hipSetDevice(ctx->device));
+    const size_t off = align_up(sizeof(FrameDev) * nf);
+    HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    HIP_TRY(hipMemcpy(out, static_cast<const char*>(ws) + off, sizeof(uint32_t) * SD7_CNT_WORDS * nf,
+                      hipMemcpyDeviceToHost));
+    return SD7_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,453 @@
+// Tile binning with a depth sort (the rasterizer front end of Sec. 4.4):
+//   1. depth sort: stable LSD radix sort (4 x 8-bit digits) of the kept
+//      Gaussians by the bits of their FP32 depth (positive floats order like
+//      their bit patterns), values = frame-local Gaussian index; the first
+//      pass also drops culled Gaussians (compaction).
+//   2. exclusive scan of the tiles each sorted Gaussian touches -> pair offsets.
+//   3. emit: every output pair (tile, Gaussian) is written by one lane
+//      (load-balanced over pairs, not over Gaussians), staged in LDS and
+//      stored coalesced; pairs come out in depth order.
+//   4. tile sort: stable LSD radix sort of the pairs by tile id; stability
+//      keeps the depth order inside each tile, so each tile list is ordered by
+//      (depth bits, Gaussian index).
+//   5. ranges: [begin, end) of every tile's list.
+// Every stage is segmented by frame: a frame's elements never mix with
+// another frame's, so a frame bins identically alone and in a batch.
+// Sizes that depend on the data (kept Gaussians, pairs) stay on the device;
+// the kernels that need them run persistent grids over work tiles.
+#include "common.h"
+
+namespace sd7 {
+
+// ---------------------------------------------------------------------------
+// block-wide exclusive scan of one value per thread (256 threads)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_tmp, uint32_t& total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t v = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_up(v, off);
+        if (lane >= off) v += t;
+    }
+    if (lane == 63) s_tmp[wave] = v;
+    __syncthreads();
+    uint32_t before = 0;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t s = s_tmp[w];
+        if (w < wave) before += s;
+        total += s;
+    }
+    __syncthreads();
+    return before + v - x;
+}
+
+// ---------------------------------------------------------------------------
+// device-wide exclusive scan (reduce, spine, down-sweep); length given either
+// on the host (len_dev == nullptr) or in device memory.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ in, uint32_t len_host,
+                                                     const uint32_t* __restrict__ len_dev,
+                                                     uint32_t* __restrict__ partials)
+{
+    __shared__ uint32_t s_tmp[4];
+    const uint32_t len = len_dev ? *len_dev : len_host;
+    const uint32_t ntiles = (len + kScanItems - 1) / kScanItems;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint32_t base = t * kScanItems + threadIdx.x * 16;
+        uint32_t s = 0;
+        if (base + 16 <= len) {
+            const uint4* p = reinterpret_cast<const uint4*>(in + base);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint4 q = p[k];
+                s += q.x + q.y + q.z + q.w;
+            }
+        } else {
+            for (uint32_t e = base; e < len && e < base + 16; ++e) s += in[e];
+        }
+        uint32_t total;
+        block_excl_scan(s, s_tmp, total);
+        if (threadIdx.x == 0) partials[t] = total;
+    }
+}
+
+// One block: exclusive scan of the partials in place; the grand total goes to
+// partials[ntiles] and, if requested, to *total_out.
+__global__ __launch_bounds__(1024) void k_scan_spine(uint32_t* __restrict__ partials, uint32_t len_host,
+                                                     const uint32_t* __restrict__ len_dev,
+                                                     uint32_t* __restrict__ total_out)
+{
+    __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_carry;
+    const uint32_t len = len_dev ? *len_dev : len_host;
+    const uint32_t ntiles = (len + kScanItems - 1) / kScanItems;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < ntiles; base += 1024) {
+        const uint32_t e = base + threadIdx.x;
+        const uint32_t x = e < ntiles ? partials[e] : 0;
+        uint32_t v = x;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t t = __shfl_up(v, off);
+            if (lane >= off) v += t;
+        }
+        if (lane == 63) s_w[wave] = v;
+        __syncthreads();
+        uint32_t before = s_carry, tot = s_carry;
+        for (int w = 0; w < 16; ++w) {
+            if (w < wave) before += s_w[w];
+            tot += s_w[w];
+        }
+        if (e < ntiles) partials[e] = before + v - x;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry = tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partials[ntiles] = s_carry;
+        if (total_out) *total_out = s_carry;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scan_down(const uint32_t* in, uint32_t* out, uint32_t len_host,
+                                                   const uint32_t* __restrict__ len_dev,
+                                                   const uint32_t* __restrict__ partials)
+{
+    __shared__ uint32_t s_tmp[4];
+    const uint32_t len = len_dev ? *len_dev : len_host;
+    const uint32_t ntiles = (len + kScanItems - 1) / kScanItems;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint32_t base = t * kScanItems + threadIdx.x * 16;
+        uint32_t v[16];
+        const bool full = base + 16 <= len;
+        if (full) {
+            const uint4* p = reinterpret_cast<const uint4*>(in + base);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint4 q = p[k];
+                v[4 * k] = q.x; v[4 * k + 1] = q.y; v[4 * k + 2] = q.z; v[4 * k + 3] = q.w;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v[k] = (base + k < len) ? in[base + k] : 0;
+        }
+        uint32_t s = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) s += v[k];
+        uint32_t total;
+        uint32_t run = block_excl_scan(s, s_tmp, total) + partials[t];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const uint32_t x = v[k];
+            v[k] = run;
+            run += x;
+        }
+        if (full) {
+            uint4* p = reinterpret_cast<uint4*>(out + base);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) p[k] = make_uint4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                if (base + k < len) out[base + k] = v[k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// segmented LSD radix sort, one 8-bit digit per pass
+// histogram layout: hist[256 * seg.wt0 + digit * seg.nwt + tile_in_seg]; an
+// exclusive scan over the flat array then gives every (segment, digit, tile)
+// its first output slot, minus the elements of earlier segments.
+// ---------------------------------------------------------------------------
+template <bool FIRST>
+__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ keys,
+                                                    const SortSeg* __restrict__ segs, int nseg,
+                                                    const SortTotals* __restrict__ tot, int shift,
+                                                    uint32_t* __restrict__ hist)
+{
+    __shared__ uint32_t h[256];
+    const uint32_t nwt = tot->wt;
+    for (uint32_t w = blockIdx.x; w < nwt; w += gridDim.x) {
+        const int s = seg_of_tile(segs, nseg, w);
+        const SortSeg sg = segs[s];
+        const uint32_t k = w - sg.wt0;
+        h[threadIdx.x] = 0;
+        __syncthreads();
+        const uint32_t begin = k * kSortItems;
+        const uint32_t end = min(sg.len, begin + kSortItems);
+        for (uint32_t e = begin + threadIdx.x; e < end; e += 256) {
+            const uint32_t key = keys[sg.in_base + e];
+            if (FIRST && key == kCulled) continue;
+            atomicAdd(&h[(key >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        hist[256u * sg.wt0 + threadIdx.x * sg.nwt + k] = h[threadIdx.x];
+        __syncthreads();
+    }
+}
+
+// Stable scatter.  Wave w of a work tile owns elements [w*1024, (w+1)*1024)
+// of the tile and ranks them in 16 rounds of 64 (wave-level multisplit: eight
+// ballots find the lanes that share a digit); the per-wave digit counts are
+// then scanned across waves.
+template <bool FIRST>
+__global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ keys_in,
+                                                       const uint32_t* __restrict__ vals_in,
+                                                       uint32_t* __restrict__ keys_out,
+                                                       uint32_t* __restrict__ vals_out,
+                                                       const SortSeg* __restrict__ segs, int nseg,
+                                                       const SortTotals* __restrict__ tot, int shift,
+                                                       const uint32_t* __restrict__ hist)
+{
+    __shared__ uint32_t s_goff[256];
+    __shared__ uint32_t s_wh[4][256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t lt = lanemask_lt();
+    const uint32_t nwt = tot->wt;
+    for (uint32_t w = blockIdx.x; w < nwt; w += gridDim.x) {
+        const int s = seg_of_tile(segs, nseg, w);
+        const SortSeg sg = segs[s];
+        const uint32_t k = w - sg.wt0;
+        s_goff[tid] = hist[256u * sg.wt0 + tid * sg.nwt + k] - sg.cnt_excl + sg.out_base;
+        s_wh[0][tid] = 0; s_wh[1][tid] = 0; s_wh[2][tid] = 0; s_wh[3][tid] = 0;
+        __syncthreads();
+        const uint32_t wbase = k * kSortItems + wave * 1024;
+        uint32_t key[16], val[16], rank[16];
+        uint32_t okmask = 0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const uint32_t e = wbase + r * 64 + lane;
+            bool ok = e < sg.len;
+            const uint32_t kk = ok ? keys_in[sg.in_base + e] : 0u;
+            if (FIRST) ok = ok && kk != kCulled;
+            const uint32_t vv = FIRST ? e : (ok ? vals_in[sg.in_base + e] : 0u);
+            const uint32_t d = (kk >> shift) & 255u;
+            uint64_t peers = __ballot(ok);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bb = __ballot(bit);
+                peers &= bit ? bb : ~bb;
+            }
+            const uint32_t below = __popcll(peers & lt);
+            uint32_t prev = 0;
+            if (ok) prev = s_wh[wave][d];
+            if (ok && below == 0) s_wh[wave][d] = prev + __popcll(peers);
+            key[r] = kk;
+            val[r] = vv;
+            rank[r] = prev + below;
+            okmask |= (ok ? 1u : 0u) << r;
+        }
+        __syncthreads();
+        {
+            uint32_t run = 0;
+#pragma unroll
+            for (int w2 = 0; w2 < 4; ++w2) {
+                const uint32_t t = s_wh[w2][tid];
+                s_wh[w2][tid] = run;
+                run += t;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            if ((okmask >> r) & 1u) {
+                const uint32_t d = (key[r] >> shift) & 255u;
+                const uint32_t p = s_goff[d] + s_wh[wave][d] + rank[r];
+                keys_out[p] = key[r];
+                vals_out[p] = val[r];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// set-up, gather, emit, ranges
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u32(uint32_t* __restrict__ p, size_t count, uint32_t value)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+// Segments of the depth sort.  segs_all: every Gaussian (the compacting first
+// pass); segs_kept: the kept ones.
+__global__ void k_setup_depth(const FrameDev* __restrict__ tab, int nf, const uint32_t* __restrict__ counts,
+                              SortSeg* __restrict__ segs_all, SortTotals* __restrict__ tot_all,
+                              SortSeg* __restrict__ segs_kept, SortTotals* __restrict__ tot_kept)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint32_t wt_all = 0, wt_kept = 0, excl = 0;
+    for (int f = 0; f < nf; ++f) {
+        const uint32_t n = tab[f].n, g0 = tab[f].g0;
+        const uint32_t kept = counts[f * SD7_CNT_WORDS + SD7_CNT_KEPT];
+        SortSeg a;
+        a.in_base = g0; a.out_base = g0; a.len = n; a.wt0 = wt_all;
+        a.nwt = (n + kSortItems - 1) / kSortItems; a.cnt_excl = excl; a.pad[0] = a.pad[1] = 0;
+        SortSeg b = a;
+        b.len = kept; b.wt0 = wt_kept; b.nwt = (kept + kSortItems - 1) / kSortItems;
+        segs_all[f] = a;
+        segs_kept[f] = b;
+        wt_all += a.nwt;
+        wt_kept += b.nwt;
+        excl += kept;
+    }
+    tot_all->wt = wt_all; tot_all->hist_len = 256u * wt_all;
+    tot_kept->wt = wt_kept; tot_kept->hist_len = 256u * wt_kept;
+}
+
+// Tiles touched by each Gaussian in depth order (0 past the kept ones).
+__global__ __launch_bounds__(kBlock) void k_gather_ntiles(const FrameDev* __restrict__ tab, BlockMap bm,
+                                                          const uint32_t* __restrict__ counts,
+                                                          const uint32_t* __restrict__ order,
+                                                          const uint2* __restrict__ rect,
+                                                          uint32_t* __restrict__ ntiles)
+{
+    const int f = frame_of_block(bm, blockIdx.x);
+    const FrameDev& F = tab[f];
+    const uint32_t j = (blockIdx.x - bm.start[f]) * kBlock + threadIdx.x;
+    if (j >= F.n) return;
+    const uint32_t kept = counts[f * SD7_CNT_WORDS + SD7_CNT_KEPT];
+    uint32_t nt = 0;
+    if (j < kept) {
+        const uint2 r = rect[F.g0 + order[F.g0 + j]];
+        nt = ((r.y & 0xFFFFu) - (r.x & 0xFFFFu)) * ((r.y >> 16) - (r.x >> 16));
+    }
+    ntiles[F.g0 + j] = nt;
+}
+
+// Per-frame pair counts, arena slots (each frame's share rounded up to a whole
+// number of sort work tiles) and the tile-sort segments.
+__global__ void k_setup_pairs(const FrameDev* __restrict__ tab, int nf, uint32_t n_total,
+                              const uint32_t* __restrict__ toff, const uint32_t* __restrict__ toff_total,
+                              uint32_t capacity, uint32_t* __restrict__ counts,
+                              SortSeg* __restrict__ segs, SortTotals* __restrict__ tot)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const uint32_t total = *toff_total;
+    uint32_t base = 0, wt = 0, excl = 0;
+    for (int f = 0; f < nf; ++f) {
+        const uint32_t g0 = tab[f].g0, n = tab[f].n;
+        const uint32_t lo = g0 < n_total ? toff[g0] : total;
+        const uint32_t hi = (g0 + n) < n_total ? toff[g0 + n] : total;
+        uint32_t P = hi - lo;
+        uint32_t* c = counts + f * SD7_CNT_WORDS;
+        c[SD7_CNT_FLAGS] &= ~SD7_FLAG_PAIR_OVERFLOW;  // binning may be re-run with a larger arena
+        if ((uint64_t)base + P > capacity) {
+            c[SD7_CNT_FLAGS] |= SD7_FLAG_PAIR_OVERFLOW;
+            c[SD7_CNT_PAIRS] = 0;
+            c[4] = P;  // pairs the frame needed
+            P = 0;
+        } else {
+            c[SD7_CNT_PAIRS] = P;
+            c[4] = P;
+        }
+        c[SD7_CNT_PAIR_BASE] = base;
+        c[5] = lo;  // scan value at the frame's first Gaussian
+        SortSeg s;
+        s.in_base = base; s.out_base = base; s.len = P; s.wt0 = wt;
+        s.nwt = (P + kSortItems - 1) / kSortItems; s.cnt_excl = excl; s.pad[0] = s.pad[1] = 0;
+        segs[f] = s;
+        wt += s.nwt;
+        excl += P;
+        base += s.nwt * kSortItems;
+    }
+    tot->wt = wt;
+    tot->hist_len = 256u * wt;
+}
+
+// Load-balanced emission: work tile w covers pairs [k*4096, (k+1)*4096) of
+// one frame; each lane finds the Gaussian of its first pair by binary search
+// over the pair offsets and walks forward.
+__global__ __launch_bounds__(256) void k_emit(const FrameDev* __restrict__ tab, const uint32_t* __restrict__ counts,
+                                              const uint32_t* __restrict__ order, const uint2* __restrict__ rect,
+                                              const uint32_t* __restrict__ toff,
+                                              const SortSeg* __restrict__ segs, int nseg,
+                                              const SortTotals* __restrict__ tot,
+                                              uint32_t* __restrict__ pair_tile, uint32_t* __restrict__ pair_g)
+{
+    __shared__ uint32_t s_t[kSortItems];
+    __shared__ uint32_t s_g[kSortItems];
+    const uint32_t nwt = tot->wt;
+    for (uint32_t w = blockIdx.x; w < nwt; w += gridDim.x) {
+        const int f = seg_of_tile(segs, nseg, w);
+        const SortSeg sg = segs[f];
+        const FrameDev& F = tab[f];
+        const uint32_t kept = counts[f * SD7_CNT_WORDS + SD7_CNT_KEPT];
+        const uint32_t lo = counts[f * SD7_CNT_WORDS + 5];
+        const uint32_t k = w - sg.wt0;
+        const uint32_t t_begin = k * kSortItems;
+        const uint32_t cnt = min((uint32_t)kSortItems, sg.len - t_begin);
+        const uint32_t o0 = t_begin + threadIdx.x * 16;
+        const uint32_t* tf = toff + F.g0;
+        const uint32_t* of = order + F.g0;
+        if (o0 < sg.len) {
+            // largest j with tf[j] - lo <= o0
+            uint32_t a = 0, b = kept - 1;
+            while (a < b) {
+                const uint32_t mid = (a + b + 1) >> 1;
+                if (tf[mid] - lo <= o0) a = mid; else b = mid - 1;
+            }
+            uint32_t j = a;
+            uint32_t start = tf[j] - lo;
+            uint32_t next = (j + 1 < kept) ? tf[j + 1] - lo : sg.len;
+            uint2 rc = rect[F.g0 + of[j]];
+            uint32_t g = of[j];
+#pragma unroll 1
+            for (int r = 0; r < 16; ++r) {
+                const uint32_t o = o0 + r;
+                if (o >= sg.len) break;
+                while (o >= next) {
+                    ++j;
+                    start = next;
+                    next = (j + 1 < kept) ? tf[j + 1] - lo : sg.len;
+                    g = of[j];
+                    rc = rect[F.g0 + g];
+                }
+                const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, wdt = (rc.y & 0xFFFFu) - x0;
+                const uint32_t l = o - start;
+                const uint32_t ty = y0 + l / wdt, tx = x0 + l % wdt;
+                s_t[threadIdx.x * 16 + r] = ty * F.tiles_x + tx;
+                s_g[threadIdx.x * 16 + r] = g;
+            }
+        }
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e < cnt; e += 256) {
+            pair_tile[sg.out_base + t_begin + e] = s_t[e];
+            pair_g[sg.out_base + t_begin + e] = s_g[e];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ranges(const FrameDev* __restrict__ tab, const uint32_t* __restrict__ pair_tile,
+                                                const SortSeg* __restrict__ segs, int nseg,
+                                                const SortTotals* __restrict__ tot, uint2* __restrict__ ranges)
+{
+    const uint32_t nwt = tot->wt;
+    for (uint32_t w = blockIdx.x; w < nwt; w += gridDim.x) {
+        const int f = seg_of_tile(segs, nseg, w);
+        const SortSeg sg = segs[f];
+        const uint32_t t0 = tab[f].t0;
+        const uint32_t ntile = tab[f].tiles_x * tab[f].tiles_y;
+        const uint32_t k = w - sg.wt0;
+        const uint32_t end = min(sg.len, (k + 1) * kSortItems);
+        for (uint32_t e = k * kSortItems + threadIdx.x; e < end; e += 256) {
+            const uint32_t i = sg.in_base + e;
+            const uint32_t t = pair_tile[i];
+            if (t >= ntile) continue;  // never true for well-formed pairs
+            if (e == 0 || pair_tile[i - 1] != t) ranges[t0 + t].x = i;
+            if (e + 1 == sg.len || pair_tile[i + 1] != t) ranges[t0 + t].y = i + 1;
+        }
+    }
+}
+
+}  // namespace sd7

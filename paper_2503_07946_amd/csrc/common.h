@@ -1,0 +1,110 @@
+// Shared device-side definitions of lib7dgs (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sd7.h"
+
+namespace sd7 {
+
+// Rasterizer constants (FP32 values; see sd7.h).
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTMin = 1e-4f;
+constexpr float kZNear = 0.2f;
+constexpr float kDilation = 0.3f;
+constexpr float kJClamp = 1.3f;
+constexpr int kTile = SD7_TILE;
+constexpr uint32_t kCulled = 0xFFFFFFFFu;
+
+constexpr int kBlock = 256;        // threads per block of the per-Gaussian kernels
+constexpr int kSortItems = 4096;   // elements per radix-sort work tile (256 threads x 16)
+constexpr int kScanItems = 4096;   // elements per scan work tile
+constexpr int kSplatFloats = 12;   // floats per splat record
+
+// Per-frame descriptor, built on the host and copied into the workspace.
+struct FrameDev {
+    const float* mu_p;
+    const float* mu_t;
+    const float* mu_d;
+    const float* L;
+    const float* alpha;
+    const float* sh;
+    float* image;
+    float* final_T;
+    uint32_t* last;
+    const float* dL_dimage;
+    float* g_mu_p;
+    float* g_mu_t;
+    float* g_mu_d;
+    float* g_L;
+    float* g_alpha;
+    float* g_sh;
+    uint32_t n;        // Gaussians
+    uint32_t g0;       // first Gaussian in the concatenated per-Gaussian arrays
+    uint32_t W, H;
+    uint32_t tiles_x, tiles_y;
+    uint32_t t0;       // first tile in the concatenated tile arrays
+    uint32_t pad0;
+    float R[9];
+    float c[3];
+    float fx, fy, cx, cy;
+    float t;
+    float d[3];
+    float lambda_t, lambda_d;
+    float bg[3];
+    float pad1[3];
+};
+
+// Prefix of launch blocks over the frames of a call (kernel argument).
+struct BlockMap {
+    uint32_t start[SD7_MAX_FRAMES + 1];
+    int nf;
+};
+
+__device__ __forceinline__ int frame_of_block(const BlockMap& bm, uint32_t b)
+{
+    int lo = 0, hi = bm.nf - 1;
+    while (lo < hi) {  // largest f with start[f] <= b
+        int mid = (lo + hi + 1) >> 1;
+        if (bm.start[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// A segment of a segmented sort: one frame's elements.
+struct SortSeg {
+    uint32_t in_base;    // first element in the input arrays
+    uint32_t out_base;   // first element in the output arrays
+    uint32_t len;        // elements read
+    uint32_t wt0;        // first work tile
+    uint32_t nwt;        // work tiles
+    uint32_t cnt_excl;   // elements counted (scattered) by earlier segments
+    uint32_t pad[2];
+};
+
+// Device-side sizes written by the setup kernels.
+struct SortTotals {
+    uint32_t wt;         // total work tiles
+    uint32_t hist_len;   // 256 * wt
+    uint32_t pad[2];
+};
+
+__device__ __forceinline__ int seg_of_tile(const SortSeg* segs, int nseg, uint32_t w)
+{
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].wt0 <= w) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt()
+{
+    const uint32_t lane = __lane_id();
+    return lane == 0 ? 0ull : ((~0ull) >> (64 - lane));
+}
+
+}  // namespace sd7

@@ -1,0 +1,330 @@
+// Perspective (EWA) projection of the conditional 3D Gaussians (Sec. 4.4),
+// footprint, depth key and degree-3 SH colour (Sec. 3, eq. 2), and the
+// reverse.  One lane per (frame, Gaussian), FP32.
+//
+// Footprint: the pixels where alpha_c exp(-q/2) >= 1/255 form the ellipse
+// q <= k, k = 2 ln(alpha_c * 255); its exact bounding box has half-widths
+// sqrt(k Sigma2D_xx), sqrt(k Sigma2D_yy).  Every 16x16 tile that box touches
+// gets a (tile, Gaussian) pair, so tiles list every Gaussian that can reach
+// alpha >= 1/255 at one of their pixel centres.
+#include "common.h"
+
+namespace sd7 {
+
+// Real SH basis of degree <= 3, k = l*l + l + m, (-1)^|m| sign convention.
+__device__ __forceinline__ void sh_eval(float x, float y, float z, float Y[16])
+{
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[0] = 0.28209479177387814f;
+    Y[1] = -0.48860251190291992f * y;
+    Y[2] = 0.48860251190291992f * z;
+    Y[3] = -0.48860251190291992f * x;
+    Y[4] = 1.0925484305920792f * x * y;
+    Y[5] = -1.0925484305920792f * y * z;
+    Y[6] = 0.31539156525252005f * (2.0f * zz - xx - yy);
+    Y[7] = -1.0925484305920792f * x * z;
+    Y[8] = 0.54627421529603959f * (xx - yy);
+    Y[9] = -0.59004358992664352f * y * (3.0f * xx - yy);
+    Y[10] = 2.8906114426405538f * x * y * z;
+    Y[11] = -0.45704579946446572f * y * (4.0f * zz - xx - yy);
+    Y[12] = 0.3731763325901154f * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+    Y[13] = -0.45704579946446572f * x * (4.0f * zz - xx - yy);
+    Y[14] = 1.4453057213202769f * z * (xx - yy);
+    Y[15] = -0.59004358992664352f * x * (xx - 3.0f * yy);
+}
+
+// d(sum_k b_k Y_k)/d(x, y, z) for coefficient vector b (one channel).
+__device__ __forceinline__ void sh_grad(float x, float y, float z, const float b[16], float g[3])
+{
+    const float xx = x * x, yy = y * y, zz = z * z;
+    const float c1 = 0.48860251190291992f, c4 = 1.0925484305920792f, c6 = 0.31539156525252005f;
+    const float c8 = 0.54627421529603959f, c9 = 0.59004358992664352f, c10 = 2.8906114426405538f;
+    const float c11 = 0.45704579946446572f, c12 = 0.3731763325901154f, c14 = 1.4453057213202769f;
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+    gy += b[1] * -c1;
+    gz += b[2] * c1;
+    gx += b[3] * -c1;
+    gx += b[4] * c4 * y;            gy += b[4] * c4 * x;
+    gy += b[5] * -c4 * z;           gz += b[5] * -c4 * y;
+    gx += b[6] * c6 * -2.f * x;     gy += b[6] * c6 * -2.f * y;     gz += b[6] * c6 * 4.f * z;
+    gx += b[7] * -c4 * z;           gz += b[7] * -c4 * x;
+    gx += b[8] * c8 * 2.f * x;      gy += b[8] * c8 * -2.f * y;
+    gx += b[9] * -c9 * 6.f * x * y; gy += b[9] * -c9 * (3.f * xx - 3.f * yy);
+    gx += b[10] * c10 * y * z;      gy += b[10] * c10 * x * z;      gz += b[10] * c10 * x * y;
+    gx += b[11] * -c11 * (-2.f * x * y);
+    gy += b[11] * -c11 * (4.f * zz - xx - 3.f * yy);
+    gz += b[11] * -c11 * (8.f * y * z);
+    gx += b[12] * c12 * (-6.f * x * z);
+    gy += b[12] * c12 * (-6.f * y * z);
+    gz += b[12] * c12 * (6.f * zz - 3.f * xx - 3.f * yy);
+    gx += b[13] * -c11 * (4.f * zz - 3.f * xx - yy);
+    gy += b[13] * -c11 * (-2.f * x * y);
+    gz += b[13] * -c11 * (8.f * x * z);
+    gx += b[14] * c14 * 2.f * x * z; gy += b[14] * c14 * -2.f * y * z; gz += b[14] * c14 * (xx - yy);
+    gx += b[15] * -c9 * (3.f * xx - 3.f * yy); gy += b[15] * -c9 * (-6.f * x * y);
+    g[0] = gx; g[1] = gy; g[2] = gz;
+}
+
+struct Proj {
+    float x[3];     // camera coordinates
+    float u, v;     // mean2d
+    float rx, ry;   // ratios used in J (clamped)
+    bool clx, cly;  // ratio clamped
+    float M[2][3];  // J R
+    float S[3][3];  // Sigma_c
+    float s00, s01, s11, det;
+    float a, b, c;  // conic
+};
+
+__device__ __forceinline__ bool project_one(const FrameDev& F, const float m[3], const float cv[6], Proj& p)
+{
+    const float dm0 = m[0] - F.c[0], dm1 = m[1] - F.c[1], dm2 = m[2] - F.c[2];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) p.x[r] = F.R[3 * r] * dm0 + F.R[3 * r + 1] * dm1 + F.R[3 * r + 2] * dm2;
+    const float z = p.x[2];
+    if (!(z > kZNear)) return false;
+    const float fx = F.fx, fy = F.fy;
+    p.u = fx * p.x[0] / z + F.cx;
+    p.v = fy * p.x[1] / z + F.cy;
+    const float limx = kJClamp * (0.5f * (float)F.W) / fx;
+    const float limy = kJClamp * (0.5f * (float)F.H) / fy;
+    float rx = p.x[0] / z, ry = p.x[1] / z;
+    p.clx = rx >= limx || rx <= -limx;
+    p.cly = ry >= limy || ry <= -limy;
+    rx = fminf(fmaxf(rx, -limx), limx);
+    ry = fminf(fmaxf(ry, -limy), limy);
+    p.rx = rx;
+    p.ry = ry;
+    const float j00 = fx / z, j02 = -fx * rx / z, j11 = fy / z, j12 = -fy * ry / z;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        p.M[0][k] = j00 * F.R[k] + j02 * F.R[6 + k];
+        p.M[1][k] = j11 * F.R[3 + k] + j12 * F.R[6 + k];
+    }
+    p.S[0][0] = cv[0]; p.S[0][1] = p.S[1][0] = cv[1]; p.S[0][2] = p.S[2][0] = cv[2];
+    p.S[1][1] = cv[3]; p.S[1][2] = p.S[2][1] = cv[4]; p.S[2][2] = cv[5];
+    float T[2][3];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) T[r][k] = p.M[r][0] * p.S[0][k] + p.M[r][1] * p.S[1][k] + p.M[r][2] * p.S[2][k];
+    p.s00 = T[0][0] * p.M[0][0] + T[0][1] * p.M[0][1] + T[0][2] * p.M[0][2] + kDilation;
+    p.s01 = T[0][0] * p.M[1][0] + T[0][1] * p.M[1][1] + T[0][2] * p.M[1][2];
+    p.s11 = T[1][0] * p.M[1][0] + T[1][1] * p.M[1][1] + T[1][2] * p.M[1][2] + kDilation;
+    p.det = p.s00 * p.s11 - p.s01 * p.s01;
+    if (!(p.det > 0.0f)) return false;
+    p.a = p.s11 / p.det;
+    p.b = -p.s01 / p.det;
+    p.c = p.s00 / p.det;
+    return true;
+}
+
+__global__ __launch_bounds__(kBlock) void k_project(const FrameDev* __restrict__ tab, BlockMap bm,
+                                                    const float* __restrict__ mu_c, const float* __restrict__ cov_c,
+                                                    const float* __restrict__ alpha_c, float4* __restrict__ splat,
+                                                    uint2* __restrict__ rect, uint32_t* __restrict__ depth_key,
+                                                    uint32_t* __restrict__ counts)
+{
+    const int f = frame_of_block(bm, blockIdx.x);
+    const FrameDev& F = tab[f];
+    const uint32_t i = (blockIdx.x - bm.start[f]) * kBlock + threadIdx.x;
+    const bool valid = i < F.n;
+    bool keep = false;
+    if (valid) {
+        const uint32_t n = F.n;
+        const size_t g0 = F.g0;
+        const float ac = alpha_c[g0 + i];
+        float m[3], cv[6];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) m[a] = mu_c[3 * g0 + (size_t)a * n + i];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) cv[e] = cov_c[6 * g0 + (size_t)e * n + i];
+        Proj p;
+        keep = ac >= kAlphaMin && project_one(F, m, cv, p);
+        uint32_t rx0 = 0, ry0 = 0, rx1 = 0, ry1 = 0;
+        if (keep) {
+            const float k = 2.0f * logf(ac / kAlphaMin);
+            const float hx = sqrtf(k * p.s00), hy = sqrtf(k * p.s11);
+            float tx0 = floorf((p.u - hx) / (float)kTile), tx1 = floorf((p.u + hx) / (float)kTile);
+            float ty0 = floorf((p.v - hy) / (float)kTile), ty1 = floorf((p.v + hy) / (float)kTile);
+            tx0 = fmaxf(tx0, 0.0f);
+            ty0 = fmaxf(ty0, 0.0f);
+            tx1 = fminf(tx1, (float)F.tiles_x - 1.0f);
+            ty1 = fminf(ty1, (float)F.tiles_y - 1.0f);
+            keep = tx0 <= tx1 && ty0 <= ty1;  // false for NaN too
+            if (keep) {
+                rx0 = (uint32_t)tx0; ry0 = (uint32_t)ty0;
+                rx1 = (uint32_t)tx1 + 1; ry1 = (uint32_t)ty1 + 1;
+            }
+        }
+        float rgb[3] = {0.f, 0.f, 0.f};
+        if (keep) {
+            const float dx = m[0] - F.c[0], dy = m[1] - F.c[1], dz = m[2] - F.c[2];
+            const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+            float Y[16];
+            sh_eval(dx * inv, dy * inv, dz * inv, Y);
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                float s = 0.5f;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) s += F.sh[(size_t)(3 * k + ch) * n + i] * Y[k];
+                rgb[ch] = fmaxf(s, 0.0f);
+            }
+        }
+        float4* rec = splat + (g0 + i) * 3;
+        if (keep) {
+            rec[0] = make_float4(p.u, p.v, p.a, p.b);
+            rec[1] = make_float4(p.c, ac, rgb[0], rgb[1]);
+            rec[2] = make_float4(rgb[2], p.x[2], 0.f, 0.f);
+        } else {
+            rec[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+            rec[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+            rec[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        rect[g0 + i] = make_uint2(rx0 | (ry0 << 16), rx1 | (ry1 << 16));
+        depth_key[g0 + i] = keep ? __float_as_uint(p.x[2]) : kCulled;
+    }
+    const uint64_t kept = __ballot(keep);
+    if (__lane_id() == 0 && kept) atomicAdd(&counts[f * SD7_CNT_WORDS + SD7_CNT_KEPT], (uint32_t)__popcll(kept));
+}
+
+// Reverse of k_project.  d_splat planes per frame: (du, dv, da, db, dc, dop,
+// dr, dg, db) where db is the derivative w.r.t. the conic b of
+// q = a dx^2 + 2 b dx dy + c dy^2.
+__global__ __launch_bounds__(kBlock) void k_project_bwd(const FrameDev* __restrict__ tab, BlockMap bm,
+                                                        const float* __restrict__ mu_c,
+                                                        const float* __restrict__ cov_c,
+                                                        const float* __restrict__ alpha_c,
+                                                        const uint32_t* __restrict__ depth_key,
+                                                        const float* __restrict__ d_splat,
+                                                        float* __restrict__ d_mu_c, float* __restrict__ d_cov_c,
+                                                        float* __restrict__ d_alpha_c)
+{
+    const int f = frame_of_block(bm, blockIdx.x);
+    const FrameDev& F = tab[f];
+    const uint32_t i = (blockIdx.x - bm.start[f]) * kBlock + threadIdx.x;
+    if (i >= F.n) return;
+    const uint32_t n = F.n;
+    const size_t g0 = F.g0;
+    float gmu[3] = {0.f, 0.f, 0.f}, gcov[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, gac = 0.f;
+    float gsh[48];
+#pragma unroll
+    for (int k = 0; k < 48; ++k) gsh[k] = 0.f;
+    if (depth_key[g0 + i] != kCulled) {
+        float ds[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) ds[k] = d_splat[9 * g0 + (size_t)k * n + i];
+        float m[3], cv[6];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) m[a] = mu_c[3 * g0 + (size_t)a * n + i];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) cv[e] = cov_c[6 * g0 + (size_t)e * n + i];
+        Proj p;
+        project_one(F, m, cv, p);
+        gac = ds[5];
+        // colour
+        const float dx = m[0] - F.c[0], dy = m[1] - F.c[1], dz = m[2] - F.c[2];
+        const float len = sqrtf(dx * dx + dy * dy + dz * dz);
+        const float inv = 1.0f / len;
+        const float dir[3] = {dx * inv, dy * inv, dz * inv};
+        float Y[16];
+        sh_eval(dir[0], dir[1], dir[2], Y);
+        float gdir[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float b[16];
+            float s = 0.5f;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                b[k] = F.sh[(size_t)(3 * k + ch) * n + i];
+                s += b[k] * Y[k];
+            }
+            const float graw = s > 0.0f ? ds[6 + ch] : 0.0f;
+            if (graw != 0.0f) {
+#pragma unroll
+                for (int k = 0; k < 16; ++k) gsh[3 * k + ch] = graw * Y[k];
+                float g[3];
+                sh_grad(dir[0], dir[1], dir[2], b, g);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) gdir[a] += graw * g[a];
+            }
+        }
+        const float dd = dir[0] * gdir[0] + dir[1] * gdir[1] + dir[2] * gdir[2];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gmu[a] += (gdir[a] - dir[a] * dd) * inv;
+
+        // conic (a, b, c) = inverse of Sigma2D -> d(s00, s01, s11)
+        const float ga = ds[2], gb = ds[3], gc = ds[4];
+        const float A = p.a, B = p.b, C = p.c;
+        const float g00 = -(ga * A * A + gb * A * B + gc * B * B);
+        const float g11 = -(ga * B * B + gb * B * C + gc * C * C);
+        const float g01 = -(2.f * ga * A * B + gb * (A * C + B * B) + 2.f * gc * B * C);
+        // symmetric 2x2 gradient of Sigma2D (entries independent)
+        const float G2[2][2] = {{g00, 0.5f * g01}, {0.5f * g01, g11}};
+        // dSigma_c = M^T G2 M
+        float GM[2][3];
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) GM[r][k] = G2[r][0] * p.M[0][k] + G2[r][1] * p.M[1][k];
+        float Gs[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b2 = 0; b2 < 3; ++b2) Gs[a][b2] = p.M[0][a] * GM[0][b2] + p.M[1][a] * GM[1][b2];
+        gcov[0] = Gs[0][0];
+        gcov[1] = Gs[0][1] + Gs[1][0];
+        gcov[2] = Gs[0][2] + Gs[2][0];
+        gcov[3] = Gs[1][1];
+        gcov[4] = Gs[1][2] + Gs[2][1];
+        gcov[5] = Gs[2][2];
+        // dM = 2 G2 M Sigma_c ; dJ = dM R^T
+        float dM[2][3];
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                dM[r][k] = 2.f * (GM[r][0] * p.S[0][k] + GM[r][1] * p.S[1][k] + GM[r][2] * p.S[2][k]);
+        float dJ[2][3];
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                dJ[r][q] = dM[r][0] * F.R[3 * q] + dM[r][1] * F.R[3 * q + 1] + dM[r][2] * F.R[3 * q + 2];
+        const float fx = F.fx, fy = F.fy;
+        const float x = p.x[0], y = p.x[1], z = p.x[2];
+        const float iz = 1.0f / z, iz2 = iz * iz;
+        float gx = 0.f, gy = 0.f, gz = 0.f;
+        // J00 = fx/z, J02 = -fx rx/z, J11 = fy/z, J12 = -fy ry/z
+        gz += dJ[0][0] * (-fx * iz2) + dJ[1][1] * (-fy * iz2);
+        if (!p.clx) {
+            gx += dJ[0][2] * (-fx * iz2);
+            gz += dJ[0][2] * (2.f * fx * x * iz2 * iz);
+        } else {
+            gz += dJ[0][2] * (fx * p.rx * iz2);
+        }
+        if (!p.cly) {
+            gy += dJ[1][2] * (-fy * iz2);
+            gz += dJ[1][2] * (2.f * fy * y * iz2 * iz);
+        } else {
+            gz += dJ[1][2] * (fy * p.ry * iz2);
+        }
+        // mean2d
+        gx += ds[0] * fx * iz;
+        gz += ds[0] * (-fx * x * iz2);
+        gy += ds[1] * fy * iz;
+        gz += ds[1] * (-fy * y * iz2);
+        // x_cam = R (mu - c)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gmu[a] += F.R[a] * gx + F.R[3 + a] * gy + F.R[6 + a] * gz;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d_mu_c[3 * g0 + (size_t)a * n + i] = gmu[a];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) d_cov_c[6 * g0 + (size_t)e * n + i] = gcov[e];
+    d_alpha_c[g0 + i] = gac;
+#pragma unroll
+    for (int k = 0; k < 48; ++k) F.g_sh[(size_t)k * n + i] = gsh[k];
+}
+
+}  // namespace sd7

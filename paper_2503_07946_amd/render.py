@@ -1,0 +1,305 @@
+"""PyTorch-facing wrapper of lib7dgs.  PyTorch provides device memory and
+streams; every step of the render path runs in the HIP library."""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+PARAMS = ("mu_p", "mu_t", "mu_d", "L", "alpha", "sh")
+SHAPES = {"mu_p": 3, "mu_t": 1, "mu_d": 3, "L": 28, "alpha": 1, "sh": 48}
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+class GaussianScene:
+    """A scene of 7D Gaussians resident in device memory (FP32 planes)."""
+
+    def __init__(self, mu_p, mu_t, mu_d, L_, alpha, sh):
+        self.mu_p, self.mu_t, self.mu_d, self.L, self.alpha, self.sh = mu_p, mu_t, mu_d, L_, alpha, sh
+        n = int(mu_t.shape[0])
+        for k in PARAMS:
+            t = getattr(self, k)
+            if t.dtype != torch.float32 or not t.is_contiguous() or t.device.type != "cuda":
+                raise ValueError(f"{k}: need a contiguous float32 device tensor")
+            if t.numel() != SHAPES[k] * n:
+                raise ValueError(f"{k}: expected {SHAPES[k]} x {n} values, got {tuple(t.shape)}")
+
+    @classmethod
+    def from_host(cls, scene, device="cuda"):
+        arrs = scene.arrays() if hasattr(scene, "arrays") else scene
+        return cls(*(torch.as_tensor(np.ascontiguousarray(arrs[k], np.float32)).to(device)
+                     for k in PARAMS))
+
+    @property
+    def n(self) -> int:
+        return int(self.mu_t.shape[0])
+
+    @property
+    def device(self):
+        return self.mu_t.device
+
+    def nbytes(self) -> int:
+        return 84 * 4 * self.n
+
+    def sd7(self) -> L.Sd7Scene:
+        return L.Sd7Scene(*(_ptr(getattr(self, k)) for k in PARAMS), self.n)
+
+
+def view_struct(v) -> L.Sd7View:
+    s = L.Sd7View()
+    s.R_wc[:] = [float(x) for x in np.asarray(v.R_wc, np.float32).reshape(9)]
+    s.c[:] = [float(x) for x in np.asarray(v.c, np.float32).reshape(3)]
+    s.fx, s.fy, s.cx, s.cy = float(v.fx), float(v.fy), float(v.cx), float(v.cy)
+    s.W, s.H = int(v.W), int(v.H)
+    s.t = float(v.t)
+    s.d[:] = [float(x) for x in np.asarray(v.d, np.float32).reshape(3)]
+    s.lambda_t, s.lambda_d = float(v.lambda_t), float(v.lambda_d)
+    s.bg[:] = [float(x) for x in np.asarray(v.bg, np.float32).reshape(3)]
+    return s
+
+
+@dataclass
+class FrameIO:
+    scene: GaussianScene
+    view: object
+    image: torch.Tensor
+    final_T: torch.Tensor
+    last: torch.Tensor
+    dL_dimage: torch.Tensor | None = None
+    grads: dict | None = None
+
+
+@dataclass
+class Batch:
+    """One call's frames, their outputs and the workspace."""
+    frames: list
+    cstruct: object
+    nf: int
+    capacity: int
+    layout: L.Sd7Layout
+    ws: torch.Tensor
+    counts_host: np.ndarray | None = None
+    extra: dict = field(default_factory=dict)
+
+    # ---- typed views of workspace arrays (frame f) -------------------------
+    def _arr(self, off, dtype, count, offset_elems=0):
+        itemsize = torch.tensor([], dtype=dtype).element_size()
+        start = int(off) + itemsize * int(offset_elems)
+        return self.ws[start:start + itemsize * int(count)].view(dtype)
+
+    def g0(self, f):
+        return int(self.layout.g0[f])
+
+    def planes(self, name, k, f):
+        n = self.frames[f].scene.n
+        return self._arr(getattr(self.layout, name), torch.float32, k * n, k * self.g0(f)).view(k, n)
+
+    def mu_c(self, f=0):
+        return self.planes("off_mu_c", 3, f)
+
+    def cov_c(self, f=0):
+        return self.planes("off_cov_c", 6, f)
+
+    def alpha_c(self, f=0):
+        return self.planes("off_alpha_c", 1, f)[0]
+
+    def splat(self, f=0):
+        n = self.frames[f].scene.n
+        return self._arr(self.layout.off_splat, torch.float32, 12 * n, 12 * self.g0(f)).view(n, 12)
+
+    def rect(self, f=0):
+        n = self.frames[f].scene.n
+        return self._arr(self.layout.off_rect, torch.int32, 2 * n, 2 * self.g0(f)).view(n, 2)
+
+    def depth_key(self, f=0):
+        n = self.frames[f].scene.n
+        return self._arr(self.layout.off_depth_key, torch.int32, n, self.g0(f))
+
+    def order(self, f=0):
+        n = self.frames[f].scene.n
+        return self._arr(self.layout.off_order, torch.int32, n, self.g0(f))
+
+    def counts(self):
+        return self._arr(self.layout.off_counts, torch.int32, self.nf * L.SD7_CNT_WORDS).view(
+            self.nf, L.SD7_CNT_WORDS)
+
+    def pairs(self, f=0, counts=None):
+        c = self.counts().cpu().numpy() if counts is None else counts
+        base, P = int(c[f, L.SD7_CNT_PAIR_BASE]), int(c[f, L.SD7_CNT_PAIRS])
+        t = self._arr(self.layout.off_pair_tile, torch.int32, P, base)
+        g = self._arr(self.layout.off_pair_g, torch.int32, P, base)
+        return t, g, base
+
+    def ranges(self, f=0):
+        v = self.frames[f].view
+        T = ((v.W + 15) // 16) * ((v.H + 15) // 16)
+        return self._arr(self.layout.off_ranges, torch.int32, 2 * T, 2 * int(self.layout.tile0[f])).view(T, 2)
+
+    def d_splat(self, f=0):
+        return self.planes("off_d_splat", 9, f)
+
+
+class Renderer:
+    """Owns an sd7 context on one device."""
+
+    def __init__(self, device: int | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the 7DGS render path needs a GPU (no CPU fallback)")
+        self.lib = L.load()
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(self.lib.sd7_create(self.device, ctypes.byref(h)))
+        self.ctx = h
+        self.default_capacity = 1 << 20
+
+    def close(self):
+        if self.ctx:
+            self.lib.sd7_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- batch construction ------------------------------------------------
+    def make_frames(self, items, outputs=None, need_grad=False) -> list:
+        frames = []
+        dev = torch.device("cuda", self.device)
+        for k, (scene, view) in enumerate(items):
+            H, W = int(view.H), int(view.W)
+            if outputs is not None:
+                img, T, last = outputs[k]
+            else:
+                img = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+                T = torch.empty((H, W), dtype=torch.float32, device=dev)
+                last = torch.empty((H, W), dtype=torch.int32, device=dev)
+            fr = FrameIO(scene, view, img, T, last)
+            if need_grad:
+                fr.grads = {k2: torch.empty_like(getattr(scene, k2)) for k2 in PARAMS}
+            frames.append(fr)
+        return frames
+
+    @staticmethod
+    def cstruct(frames):
+        arr = (L.Sd7Frame * len(frames))()
+        for i, fr in enumerate(frames):
+            c = arr[i]
+            c.scene = fr.scene.sd7()
+            c.view = view_struct(fr.view)
+            c.image, c.final_T, c.last = _ptr(fr.image), _ptr(fr.final_T), _ptr(fr.last)
+            c.dL_dimage = _ptr(fr.dL_dimage)
+            if fr.grads is not None:
+                c.grad = L.Sd7SceneGrad(*(_ptr(fr.grads[k]) for k in PARAMS))
+        return arr
+
+    def plan(self, frames, capacity: int) -> L.Sd7Layout:
+        cs = self.cstruct(frames)
+        lay = L.Sd7Layout()
+        L.check(self.lib.sd7_plan(cs, len(frames), int(capacity), ctypes.byref(lay)))
+        return lay
+
+    def batch(self, frames, capacity: int, ws: torch.Tensor | None = None) -> Batch:
+        cs = self.cstruct(frames)
+        lay = L.Sd7Layout()
+        L.check(self.lib.sd7_plan(cs, len(frames), int(capacity), ctypes.byref(lay)))
+        if ws is None or ws.numel() < lay.bytes:
+            ws = torch.empty(int(lay.bytes), dtype=torch.uint8, device=torch.device("cuda", self.device))
+        return Batch(frames, cs, len(frames), int(capacity), lay, ws)
+
+    def stage(self, name: str, b: Batch, stream=None):
+        st = torch.cuda.current_stream(self.device) if stream is None else stream
+        fn = getattr(self.lib, name)
+        L.check(fn(self.ctx, b.cstruct, b.nf, b.capacity, ctypes.c_void_p(b.ws.data_ptr()),
+                   b.ws.numel(), ctypes.c_void_p(st.cuda_stream)))
+
+    def read_counts(self, b: Batch, stream=None) -> np.ndarray:
+        st = torch.cuda.current_stream(self.device) if stream is None else stream
+        out = (ctypes.c_uint32 * (b.nf * L.SD7_CNT_WORDS))()
+        L.check(self.lib.sd7_read_counts(self.ctx, b.nf, ctypes.c_void_p(b.ws.data_ptr()), out,
+                                         ctypes.c_void_p(st.cuda_stream)))
+        b.counts_host = np.frombuffer(out, dtype=np.uint32).reshape(b.nf, L.SD7_CNT_WORDS).copy()
+        return b.counts_host
+
+    # ---- whole renders -------------------------------------------------------
+    def render_frames(self, frames, capacity: int | None = None, stream=None,
+                      exact: bool = True) -> Batch:
+        """slice, project, bin, rasterize.  With exact=True the pair counts are
+        read back after binning (one host sync) and binning is redone with a
+        larger arena if a frame overflowed."""
+        cap = self.default_capacity if capacity is None else int(capacity)
+        b = self.batch(frames, cap)
+        for s in ("sd7_slice", "sd7_project", "sd7_bin"):
+            self.stage(s, b, stream)
+        if exact:
+            c = self.read_counts(b, stream)
+            if np.any(c[:, L.SD7_CNT_FLAGS] & L.SD7_FLAG_PAIR_OVERFLOW):
+                need = int(sum((int(x) + 4095) // 4096 * 4096 for x in c[:, L.SD7_CNT_NEEDED]))
+                b2 = self.batch(frames, need)
+                prefix = int(b.layout.off_pair_tile)
+                b2.ws[:prefix].copy_(b.ws[:prefix])
+                b = b2
+                self.stage("sd7_bin", b, stream)
+                self.default_capacity = max(self.default_capacity, need)
+        self.stage("sd7_rasterize", b, stream)
+        return b
+
+    def render(self, scene: GaussianScene, view, capacity=None, stream=None) -> Batch:
+        return self.render_frames(self.make_frames([(scene, view)]), capacity, stream)
+
+    def backward(self, b: Batch, dL_dimages, stream=None):
+        """Reverse pass of a rendered batch: returns per-frame gradient dicts."""
+        for fr, g in zip(b.frames, dL_dimages):
+            fr.dL_dimage = g.contiguous()
+            if fr.grads is None:
+                fr.grads = {k: torch.empty_like(getattr(fr.scene, k)) for k in PARAMS}
+        b.cstruct = self.cstruct(b.frames)
+        for s in ("sd7_rasterize_backward", "sd7_project_backward", "sd7_slice_backward"):
+            self.stage(s, b, stream)
+        return [fr.grads for fr in b.frames]
+
+
+_RENDERERS: dict = {}
+
+
+def get_renderer(device=None) -> Renderer:
+    dev = torch.cuda.current_device() if device is None else int(device)
+    r = _RENDERERS.get(dev)
+    if r is None:
+        r = _RENDERERS[dev] = Renderer(dev)
+    return r
+
+
+class Render7DGS(torch.autograd.Function):
+    """image = render(mu_p, mu_t, mu_d, L, alpha, sh; view).  The backward runs
+    the library's reverse kernels (compositing recomputed front to back, no
+    per-pixel list state saved)."""
+
+    @staticmethod
+    def forward(ctx, mu_p, mu_t, mu_d, L_, alpha, sh, view):
+        r = get_renderer(mu_p.device.index)
+        scene = GaussianScene(*(t.detach().contiguous() for t in (mu_p, mu_t, mu_d, L_, alpha, sh)))
+        b = r.render_frames(r.make_frames([(scene, view)]))
+        ctx.batch = b
+        ctx.renderer = r
+        return b.frames[0].image
+
+    @staticmethod
+    def backward(ctx, dimage):
+        g = ctx.renderer.backward(ctx.batch, [dimage.contiguous()])[0]
+        ctx.batch = None
+        return g["mu_p"], g["mu_t"], g["mu_d"], g["L"], g["alpha"], g["sh"], None
+
+
+def render_image(params: dict, view) -> torch.Tensor:
+    return Render7DGS.apply(params["mu_p"], params["mu_t"], params["mu_d"], params["L"],
+                            params["alpha"], params["sh"], view)

@@ -19,3 +19,20 @@ def _oracle_built():
     if not os.path.exists(oracle.LIB_PATH):
         oracle.build()
     yield
+
+
+@pytest.fixture
+def report(request):
+    """Append measured parity figures to gpurun_out/parity_report.jsonl (when
+    that directory exists) so runs on the GPU machine leave a record."""
+    import json
+    import time
+    path = os.path.join(ROOT, "gpurun_out", "parity_report.jsonl")
+
+    def _rep(kind, **kw):
+        rec = {"test": request.node.nodeid, "kind": kind, "time": time.time(), **kw}
+        print(json.dumps(rec, default=float), flush=True)
+        if os.path.isdir(os.path.dirname(path)):
+            with open(path, "a") as f:
+                f.write(json.dumps(rec, default=float) + "\n")
+    return _rep

@@ -1,0 +1,172 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark
+times (a batch of 16 frames of 800x800 over 200,000 Gaussians), checked on
+outputs the oracle can compute at this size: the whole slice, the integer
+stage re-executed on the CPU, and sampled pixel crops of the image.  Also the
+training workload (500,000 Gaussians at 1352x1014, forward + backward with the
+upstream gradient restricted to a crop) and the ill-conditioned 4M-Gaussian
+1080p stress scene."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.grad as og
+import scenegen
+from tests.gpu_helpers import cpu_bin, image_check, slice_tolerance
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_07946_amd.render import get_renderer
+    return get_renderer(0)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return scenegen.config1(16)
+
+
+@pytest.fixture(scope="module")
+def c1_batch(R, c1):
+    from paper_2503_07946_amd.render import GaussianScene
+    scene, views = c1
+    gs = GaussianScene.from_host(scene)
+    print("[fullsize] 200k Gaussians, batch of 16 x 800x800", flush=True)
+    b = R.render_frames(R.make_frames([(gs, v) for v in views]))
+    torch.cuda.synchronize()
+    return b
+
+
+def test_c1_slice_all_gaussians(R, c1, c1_batch):
+    scene, views = c1
+    for f in (0, 9):
+        ora = oracle.slice_(scene, views[f])
+        mu = c1_batch.mu_c(f).cpu().numpy().astype(np.float64)
+        cov = c1_batch.cov_c(f).cpu().numpy().astype(np.float64)
+        ac = c1_batch.alpha_c(f).cpu().numpy().astype(np.float64)
+        mscale = np.maximum(np.abs(ora.mu_c).max(0), np.abs(scene.mu_p).max(0))
+        assert np.all(np.abs(mu - ora.mu_c) <= slice_tolerance(ora.mu_c, mscale))
+        assert np.all(np.abs(cov - ora.cov_c) <= slice_tolerance(ora.cov_c, np.abs(ora.cov_c).max(0)))
+        assert np.all(np.abs(ac - ora.alpha_c) <= slice_tolerance(ora.alpha_c, ora.alpha_c))
+
+
+def test_c1_integer_stage_bitexact(R, c1, c1_batch, report):
+    scene, views = c1
+    counts = c1_batch.counts().cpu().numpy()
+    for f in (0, 15):
+        v = views[f]
+        dk = c1_batch.depth_key(f).cpu().numpy().view(np.uint32)
+        rect = c1_batch.rect(f).cpu().numpy().view(np.uint32)
+        order, tile, g, ranges = cpu_bin(dk, rect, 50, 2500)
+        kept = int(counts[f, 0])
+        assert kept == len(order)
+        assert np.array_equal(c1_batch.order(f).cpu().numpy()[:kept], order)
+        t_gpu, g_gpu, base = c1_batch.pairs(f, counts)
+        assert np.array_equal(t_gpu.cpu().numpy(), tile)
+        assert np.array_equal(g_gpu.cpu().numpy(), g)
+        rg = c1_batch.ranges(f).cpu().numpy().astype(np.int64)
+        ne = ranges[:, 1] > ranges[:, 0]
+        assert np.array_equal(rg[ne] - base, ranges[ne])
+        report("c1_bin", frame=f, kept=kept, pairs=len(tile))
+
+
+def test_c1_sampled_crops(R, c1, c1_batch, report):
+    scene, views = c1
+    rng = np.random.default_rng(11)
+    for f in (0, 7):
+        v = views[f]
+        img = c1_batch.frames[f].image.cpu().numpy()
+        for _ in range(2):
+            x0, y0 = int(rng.integers(0, 800 - 32)), int(rng.integers(0, 800 - 32))
+            crop = (x0, y0, 32, 32)
+            ora = oracle.render(scene, v, crop=crop)
+            err, nflag = image_check(img[:, y0:y0 + 32, x0:x0 + 32], ora)
+            report("c1_crop", frame=f, crop=crop, max_err=err, flagged=nflag)
+            assert err <= 1e-4
+        # the centre crop, where the tile lists are longest
+        crop = (384, 384, 32, 32)
+        ora = oracle.render(scene, v, crop=crop)
+        err, nflag = image_check(img[:, 384:416, 384:416], ora)
+        report("c1_crop", frame=f, crop=crop, max_err=err, flagged=nflag)
+        assert err <= 1e-4
+
+
+def test_c2_training_step_crop_gradients(R, report):
+    """500,000 Gaussians at 1352x1014; L1 loss gradient kept on a 32x32 crop;
+    every Gaussian's gradient compared with the FP64 reference."""
+    from paper_2503_07946_amd.render import GaussianScene
+    scene, views, target = scenegen.config2()
+    v = views[0]
+    gs = GaussianScene.from_host(scene)
+    print("[fullsize] c2 forward", flush=True)
+    b = R.render(gs, v)
+    img = b.frames[0].image.cpu().numpy()
+    x0, y0 = 660, 490
+    crop = (x0, y0, 32, 32)
+    ora = oracle.render(scene, v, crop=crop)
+    err, nflag = image_check(img[:, y0:y0 + 32, x0:x0 + 32], ora)
+    assert err <= 1e-4
+    dL = np.zeros_like(img)
+    sub = og.l1_grad_image(img[:, y0:y0 + 32, x0:x0 + 32].astype(np.float64), target[:, y0:y0 + 32, x0:x0 + 32])
+    dL[:, y0:y0 + 32, x0:x0 + 32] = sub * (ora.flags == 0)[None]
+    print("[fullsize] c2 backward", flush=True)
+    g = R.backward(b, [torch.as_tensor(dL, device="cuda")])[0]
+    torch.cuda.synchronize()
+    g_ora, _ = og.grad(scene, v, dL[:, y0:y0 + 32, x0:x0 + 32].astype(np.float64), crop=crop)
+    rep = {}
+    for k in og.PARAMS:
+        a = g[k].cpu().numpy().astype(np.float64).reshape(g_ora[k].shape)
+        o = g_ora[k]
+        rel = np.linalg.norm(a - o) / max(np.linalg.norm(o), 1e-30)
+        rep[k] = rel
+        assert rel <= 1e-3, (k, rel)
+    report("c2_grad", max_err=err, flagged=nflag, **rep)
+
+
+def test_c4_stress_scene(R, report):
+    """4,000,000 Gaussians with (t, d) blocks of condition number up to 1e4,
+    1920x1080: slice on a sample of Gaussians, the integer stage, and a crop."""
+    from paper_2503_07946_amd.render import GaussianScene
+    print("[fullsize] generating the 4M stress scene", flush=True)
+    scene = scenegen.make_scene(4_000_000, 4, h=1.0, sigma_off=0.05, recondition=True)
+    v = scenegen.make_views(1, 4, r=3.0, W=1920, H=1080)[0]
+    gs = GaussianScene.from_host(scene)
+    print("[fullsize] c4 render", flush=True)
+    b = R.render(gs, v)
+    torch.cuda.synchronize()
+    idx = np.random.default_rng(0).choice(scene.n, 200_000, replace=False)
+    sub = scene.subset(idx)
+    ora = oracle.slice_(sub, v)
+    mu = b.mu_c().cpu().numpy()[:, idx].astype(np.float64)
+    cov = b.cov_c().cpu().numpy()[:, idx].astype(np.float64)
+    mscale = np.maximum(np.abs(ora.mu_c).max(0), np.abs(sub.mu_p).max(0))
+    assert np.all(np.abs(mu - ora.mu_c) <= slice_tolerance(ora.mu_c, mscale))
+    assert np.all(np.abs(cov - ora.cov_c) <= slice_tolerance(ora.cov_c, np.abs(ora.cov_c).max(0)))
+    counts = b.counts().cpu().numpy()
+    dk = b.depth_key().cpu().numpy().view(np.uint32)
+    rect = b.rect().cpu().numpy().view(np.uint32)
+    kept = dk != 0xFFFFFFFF
+    x0, y0 = (rect[:, 0] & 0xFFFF).astype(np.int64), (rect[:, 0] >> 16).astype(np.int64)
+    x1, y1 = (rect[:, 1] & 0xFFFF).astype(np.int64), (rect[:, 1] >> 16).astype(np.int64)
+    assert int(counts[0, 0]) == int(kept.sum())
+    assert int(counts[0, 1]) == int(((x1 - x0) * (y1 - y0))[kept].sum())
+    # sampled tiles: the list is every kept Gaussian whose box covers the
+    # tile, in (depth key, index) order
+    rg = b.ranges(0).cpu().numpy().astype(np.int64)
+    pg = b.ws[b.layout.off_pair_g:].view(torch.int32)
+    for t in np.random.default_rng(1).choice(120 * 68, 48, replace=False):
+        tx, ty = t % 120, t // 120
+        cand = np.nonzero(kept & (x0 <= tx) & (tx < x1) & (y0 <= ty) & (ty < y1))[0]
+        ref = cand[np.lexsort((cand, dk[cand]))]
+        got = pg[rg[t, 0]:rg[t, 1]].cpu().numpy() if rg[t, 1] > rg[t, 0] else np.array([], np.int64)
+        assert np.array_equal(got, ref), f"tile {t}"
+    img = b.frames[0].image.cpu().numpy()
+    crop = (952, 532, 16, 16)
+    o_img = oracle.render(scene, v, crop=crop)
+    err, nflag = image_check(img[:, 532:548, 952:968], o_img)
+    report("c4", kept=int(counts[0, 0]), pairs=int(counts[0, 1]), max_err=err, flagged=nflag)
+    assert err <= 1e-4
