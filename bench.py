@@ -42,12 +42,73 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--views", type=int, default=50)
-    ap.add_argument("--batch", type=int, default=16, help="frames per set of launches")
+    ap.add_argument("--batch", type=int, default=25, help="frames per set of launches")
     ap.add_argument("--gaussians", type=int, default=200_000)
     ap.add_argument("--plain-frames", type=int, default=20, help="frames timed one per call")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-crop", type=int, default=64)
+    ap.add_argument("--serve", type=int, default=1, help="also run the serving comparison")
+    ap.add_argument("--serve-requests", type=int, default=240)
+    ap.add_argument("--serve-warmup", type=int, default=40)
+    ap.add_argument("--serve-qps", type=float, default=0.0, help="0: 0.9x the plain path's capacity")
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--serve-sizes", type=str, default="100000,300000,1000000,2000000")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
+
+
+def copy_probe(mib: int):
+    """A plain device-to-device copy of known size, for scaling HBM counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 3}))
+    return 0
+
+
+def serve_bench(a, R, L):
+    """Serving: resident scenes, a Poisson stream of (scene, camera, t) requests
+    at mixed resolutions; continuous batching vs one frame per call."""
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_2503_07946_amd import serve
+    from paper_2503_07946_amd.render import GaussianScene
+
+    sizes = [int(x) for x in a.serve_sizes.split(",")]
+    scenes = [GaussianScene.from_host(s) for s in scenegen.config3_scenes(sizes)]
+    torch.cuda.synchronize()
+    ex = serve.GpuExecutor(R, scenes, nstreams=2)
+    # learn pair counts and the plain path's service time on a calibration stream
+    cal = serve.default_requests(48, 1000.0, sizes, seed=301)
+    for r in cal:
+        ex.est[(r.scene, r.view.W, r.view.H)] = max(
+            ex.est.get((r.scene, r.view.W, r.view.H), 0),
+            int(R.read_counts(R.render_frames(R.make_frames([(scenes[r.scene], r.view)]),
+                                              capacity=ex.pair_estimate(r)))[0, L.SD7_CNT_PAIRS]))
+    t0 = time.perf_counter()
+    for r in cal:
+        ex.render_one(r)
+    plain_service = (time.perf_counter() - t0) / len(cal)
+    qps = a.serve_qps if a.serve_qps > 0 else 0.9 / plain_service
+    n = a.serve_requests + a.serve_warmup
+    reqs_p = serve.default_requests(n, qps, sizes, seed=300)
+    reqs_b = serve.default_requests(n, qps, sizes, seed=300)
+    print(f"[bench] serving: {n} requests at {qps:.1f} QPS (plain service {1e3 * plain_service:.2f} ms)",
+          file=sys.stderr, flush=True)
+    st_p = serve.run_plain(ex, reqs_p)
+    sch = serve.Scheduler(ex, serve.budget_from_gb(a.serve_budget_gb), max_slots=16, max_inflight=2)
+    st_b = sch.run(reqs_b)
+    sp, sb = st_p.summary(skip=a.serve_warmup), st_b.summary(skip=a.serve_warmup)
+    return {"qps": round(qps, 2), "requests": a.serve_requests, "scenes": sizes,
+            "resolutions": [list(r) for r in scenegen.SERVE_RES], "hbm_budget_gb": a.serve_budget_gb,
+            "plain": sp, "batched": sb}
 
 
 def pct(xs, q):
@@ -61,6 +122,8 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(multi-GPU sharding is described, not built)"}))
         return 2
+    if a.copy_probe:
+        return copy_probe(a.copy_probe)
     import numpy as np
     import torch
 
@@ -177,6 +240,8 @@ def main():
                "sample": f"{cs}x{cs} centre crop of view 0 (all 200k Gaussians sliced and projected, "
                          f"brute-force compositing), {tc:.2f} s; FPS extrapolated to the full 800x800 frame"}
 
+    serving = serve_bench(a, R, L) if a.serve else None
+
     out = {
         "metric": "rendered FPS and Mpixel/s at 1 GPU; p50/p99 frame latency, batched vs plain",
         "value": round(fps, 2), "unit": "FPS", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -193,6 +258,7 @@ def main():
         "pairs_per_view_mean": int(np.mean(pairs)), "overflowed_frames": overflow,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(out))
     return 0

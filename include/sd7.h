@@ -161,8 +161,12 @@ typedef struct {
  *   off_mu_c     float  [3 planes]             conditional mean
  *   off_cov_c    float  [6 planes]             conditional covariance (xx,xy,xz,yy,yz,zz)
  *   off_alpha_c  float  [1 plane]              conditional opacity
- *   off_splat    float  [Ntot][12]             per Gaussian: u, v, conic a, b, c,
- *                                              opacity, r, g, b, depth, 0, 0 (AoS)
+ *   off_splat    float  [Ntot][12]             per Gaussian (AoS): u, v, A, B, C, lo,
+ *                                              r, g, b, depth, alpha_c, 0 where
+ *                                              (A, B, C) = -log2(e) (a/2, b, c/2) for the
+ *                                              conic q = a dx^2 + 2b dx dy + c dy^2 and
+ *                                              lo = log2(alpha_c), so that
+ *                                              alpha_c e^{-q/2} = 2^(A dx^2 + B dx dy + C dy^2 + lo)
  *   off_rect     uint32 [Ntot][2]              tile box: (x0 | y0 << 16, x1 | y1 << 16), x1, y1 exclusive
  *   off_depth_key uint32 [Ntot]                float bits of depth; 0xFFFFFFFF = culled
  *   off_order    uint32 [Ntot]                 frame-local indices of kept Gaussians in

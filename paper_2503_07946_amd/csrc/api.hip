@@ -379,7 +379,7 @@ sd7_status do_bin(const Call& c)
 sd7_status do_raster(const Call& c)
 {
     const sd7_layout& L = c.P.L;
-    k_raster<<<c.P.tblocks, 256, 0, c.st>>>(c.tab, c.P.tmap, c.at<uint2>(L.off_ranges), c.at<uint32_t>(L.off_pair_g),
+    k_raster<<<c.P.tblocks, 64, 0, c.st>>>(c.tab, c.P.tmap, c.at<uint2>(L.off_ranges), c.at<uint32_t>(L.off_pair_g),
                                              c.at<float4>(L.off_splat));
     LAUNCH_CHECK("k_raster");
     return SD7_OK;
@@ -390,7 +390,7 @@ sd7_status do_raster_bwd(const Call& c)
     const sd7_layout& L = c.P.L;
     sd7_status s = fill(c, c.at<uint32_t>(L.off_d_splat), 9 * (size_t)L.n_total, 0);
     if (s != SD7_OK) return s;
-    k_raster_bwd<<<c.P.tblocks, 256, 0, c.st>>>(c.tab, c.P.tmap, c.at<uint2>(L.off_ranges),
+    k_raster_bwd<<<c.P.tblocks, 64, 0, c.st>>>(c.tab, c.P.tmap, c.at<uint2>(L.off_ranges),
                                                  c.at<uint32_t>(L.off_pair_g), c.at<float4>(L.off_splat),
                                                  c.at<float>(L.off_d_splat));
     LAUNCH_CHECK("k_raster_bwd");

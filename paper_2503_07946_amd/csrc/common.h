@@ -17,6 +17,10 @@ constexpr float kDilation = 0.3f;
 constexpr float kJClamp = 1.3f;
 constexpr int kTile = SD7_TILE;
 constexpr uint32_t kCulled = 0xFFFFFFFFu;
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.69314718055994531f;
+constexpr float kNegHalfLog2e = -0.72134752044448170f;
+constexpr float kNegLog2e = -1.4426950408889634f;
 
 constexpr int kBlock = 256;        // threads per block of the per-Gaussian kernels
 constexpr int kSortItems = 4096;   // elements per radix-sort work tile (256 threads x 16)

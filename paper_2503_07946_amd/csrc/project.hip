@@ -173,9 +173,10 @@ __global__ __launch_bounds__(kBlock) void k_project(const FrameDev* __restrict__
         }
         float4* rec = splat + (g0 + i) * 3;
         if (keep) {
-            rec[0] = make_float4(p.u, p.v, p.a, p.b);
-            rec[1] = make_float4(p.c, ac, rgb[0], rgb[1]);
-            rec[2] = make_float4(rgb[2], p.x[2], 0.f, 0.f);
+            // exponent of alpha in base 2: A dx^2 + B dx dy + C dy^2 + log2(alpha_c)
+            rec[0] = make_float4(p.u, p.v, kNegHalfLog2e * p.a, kNegLog2e * p.b);
+            rec[1] = make_float4(kNegHalfLog2e * p.c, log2f(ac), rgb[0], rgb[1]);
+            rec[2] = make_float4(rgb[2], p.x[2], ac, 0.f);
         } else {
             rec[0] = make_float4(0.f, 0.f, 0.f, 0.f);
             rec[1] = make_float4(0.f, 0.f, 0.f, 0.f);

@@ -1,90 +1,118 @@
 // Depth-aware, opacity-blended front-to-back compositing (Sec. 4.4) and its
-// reverse.  One 256-lane block (4 wave64) per 16x16 tile, one lane per pixel.
-// The tile list is streamed through LDS in batches of 256 splats (loaded by
-// the 256 lanes in one coalesced step, gathered by Gaussian index); the block
-// leaves as soon as every pixel is saturated.
+// reverse.
 //
-// Per (pixel, splat):  q = a dx^2 + 2 b dx dy + c dy^2 (dx = u - px),
-//   alpha = min(0.99, alpha_c exp(-q/2)); skip if alpha < 1/255;
-//   stop before the splat if T (1 - alpha) < 1e-4; C += rgb alpha T.
-// The exponent is evaluated as exp2 of -q/2 log2(e), with the conic scaled
-// once per splat when it is staged in LDS.
+// One wave64 per 16x16 tile; lane l owns a 1x4 column of pixels (x = l % 16,
+// rows 4 (l / 16) .. +3), so the column offset dx and its products are shared
+// by the lane's four pixels.  The wave walks the tile's list in order; a
+// splat record is the same for every lane, so it is read with scalar loads
+// through the scalar cache into SGPRs (no LDS staging, no barriers) and the
+// vector ALUs take it as scalar operands.  The wave leaves the list as soon
+// as all 256 pixels are saturated, and skips the blend of any splat that
+// reaches none of them.
+//
+// Per (pixel, splat), with the record's exponent coefficients
+// (A, B, C) = -(a, 2b, c) log2(e) / 2 and lo = log2(alpha_c):
+//   p = A dx^2 + B dx dy + C dy^2 + lo          (= log2 of alpha_c e^{-q/2})
+//   the splat counts at the pixel iff p >= log2(1/255);
+//   alpha = min(0.99, 2^p); w = T alpha; T' = T - w;
+//   stop before the splat if T' < 1e-4, else C += rgb w, T = T'.
 #include "common.h"
 
 namespace sd7 {
 
-constexpr float kLog2e = 1.4426950408889634f;
-constexpr float kLn2 = 0.69314718055994531f;
+constexpr float kLog2AlphaMin = -7.99435343685886f;  // log2(1/255)
+constexpr float kFar = 1e30f;                         // sample row of a finished pixel
 
-struct SplatLDS {
-    float4 p0[256];  // u, v, A, B    (A = -a log2e / 2, B = -b log2e)
-    float4 p1[256];  // C, opacity, r, g   (C = -c log2e / 2)
-    float p2[256];   // b (blue)
+struct Splat {
+    float u, v, A, B, C, lo, r, g, b;
 };
 
-__device__ __forceinline__ void stage_splat(SplatLDS& s, int slot, const float4* __restrict__ splat, size_t gi)
+__device__ __forceinline__ Splat load_splat(const float4* __restrict__ rec, uint32_t g)
 {
-    const float4* r = splat + gi * 3;
-    const float4 a = r[0], b = r[1];
-    const float bb = r[2].x;
-    s.p0[slot] = make_float4(a.x, a.y, -0.5f * kLog2e * a.z, -kLog2e * a.w);
-    s.p1[slot] = make_float4(-0.5f * kLog2e * b.x, b.y, b.z, b.w);
-    s.p2[slot] = bb;
+    const float4 p0 = rec[3 * (size_t)g];
+    const float4 p1 = rec[3 * (size_t)g + 1];
+    const float4 p2 = rec[3 * (size_t)g + 2];
+    return Splat{p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x};
 }
 
-__global__ __launch_bounds__(256) void k_raster(const FrameDev* __restrict__ tab, BlockMap bm,
-                                                const uint2* __restrict__ ranges,
-                                                const uint32_t* __restrict__ pair_g,
-                                                const float4* __restrict__ splat)
+__device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+
+__global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab, BlockMap bm,
+                                               const uint2* __restrict__ ranges,
+                                               const uint32_t* __restrict__ pair_g,
+                                               const float4* __restrict__ splat)
 {
-    __shared__ SplatLDS s;
     const int f = frame_of_block(bm, blockIdx.x);
     const FrameDev& F = tab[f];
     const uint32_t tile = blockIdx.x - bm.start[f];
     const uint32_t tx = tile % F.tiles_x, ty = tile / F.tiles_x;
-    const uint32_t px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
-    const bool inside = px < F.W && py < F.H;
-    const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t px = tx * kTile + (lane & 15);
+    const uint32_t py0 = ty * kTile + (lane >> 4) * 4;
+    const float fx = (float)px + 0.5f;
+    // A finished pixel (saturated, or outside the image) moves its sample row
+    // to kFar: its exponent becomes -inf there (C < 0), so it never passes the
+    // opacity test again and needs no flag of its own.
+    float fy[4], T[4], C0[4], C1[4], C2[4];
+    uint32_t last[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        fy[k] = (px < F.W && py0 + k < F.H) ? (float)(py0 + k) + 0.5f : kFar;
+        T[k] = 1.0f;
+        C0[k] = C1[k] = C2[k] = 0.0f;
+        last[k] = 0;
+    }
     const uint2 rg = ranges[F.t0 + tile];
-    const size_t g0 = F.g0;
-    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-    uint32_t last = 0;
-    bool done = !inside;
-    for (uint32_t b = rg.x; b < rg.y; b += 256) {
-        if (__syncthreads_count(done) == 256) break;
-        const uint32_t e = b + threadIdx.x;
-        if (e < rg.y) stage_splat(s, threadIdx.x, splat, g0 + min(pair_g[e], F.n - 1));
-        __syncthreads();
-        const int cnt = (int)min(256u, rg.y - b);
-        if (!done) {
-            for (int j = 0; j < cnt; ++j) {
-                const float4 p0 = s.p0[j];
-                const float4 p1 = s.p1[j];
-                const float dx = p0.x - fpx, dy = p0.y - fpy;
-                const float power = p0.z * dx * dx + p0.w * dx * dy + p1.x * dy * dy;
-                const float alpha = fminf(kAlphaMax, p1.y * exp2f(power));
-                if (alpha < kAlphaMin) continue;
-                const float Tn = T * (1.0f - alpha);
-                if (Tn < kTMin) {
-                    done = true;
-                    break;
-                }
-                const float wgt = alpha * T;
-                C0 += p1.z * wgt;
-                C1 += p1.w * wgt;
-                C2 += s.p2[j] * wgt;
-                T = Tn;
-                last = b - rg.x + (uint32_t)j + 1;
+    const float4* __restrict__ rec = splat + (size_t)F.g0 * 3;
+    const uint32_t gmax = __builtin_amdgcn_readfirstlane(F.n - 1);  // pairs exist only if n > 0
+    for (uint32_t e0 = rg.x; e0 < rg.y; e0 += 8) {
+        if (__ballot(fminf(fminf(fy[0], fy[1]), fminf(fy[2], fy[3])) < kFar) == 0) break;
+        const uint32_t cnt = min(8u, rg.y - e0);
+        for (uint32_t j = 0; j < cnt; ++j) {
+            const uint32_t e = e0 + j;
+            const Splat s = load_splat(rec, min(pair_g[e], gmax));
+            const float dx = s.u - fx;
+            const float base = fmaf(s.A * dx, dx, s.lo);
+            const float Bdx = s.B * dx;
+            float p[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float dy = s.v - fy[k];
+                p[k] = fmaf(dy, fmaf(s.C, dy, Bdx), base);
+            }
+            const float pmax = fmaxf(fmaxf(p[0], p[1]), fmaxf(p[2], p[3]));
+            if (__ballot(pmax >= kLog2AlphaMin) == 0) continue;
+            const uint32_t pos = e - rg.x + 1;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const bool pass = p[k] >= kLog2AlphaMin;
+                const float alpha = fminf(kAlphaMax, exp2_fast(p[k]));
+                const float w = T[k] * alpha;
+                const float Tn = T[k] - w;
+                const bool sat = Tn < kTMin;
+                const bool con = pass && !sat;
+                const float wc = con ? w : 0.0f;
+                C0[k] = fmaf(s.r, wc, C0[k]);
+                C1[k] = fmaf(s.g, wc, C1[k]);
+                C2[k] = fmaf(s.b, wc, C2[k]);
+                T[k] = con ? Tn : T[k];
+                last[k] = con ? pos : last[k];
+                fy[k] = (pass && sat) ? kFar : fy[k];
             }
         }
     }
-    if (inside) {
-        const size_t pix = (size_t)py * F.W + px, plane = (size_t)F.W * F.H;
-        F.image[pix] = C0 + T * F.bg[0];
-        F.image[plane + pix] = C1 + T * F.bg[1];
-        F.image[2 * plane + pix] = C2 + T * F.bg[2];
-        F.final_T[pix] = T;
-        F.last[pix] = last;
+    const size_t plane = (size_t)F.W * F.H;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t py = py0 + k;
+        if (px < F.W && py < F.H) {
+            const size_t pix = (size_t)py * F.W + px;
+            F.image[pix] = C0[k] + T[k] * F.bg[0];
+            F.image[plane + pix] = C1[k] + T[k] * F.bg[1];
+            F.image[2 * plane + pix] = C2[k] + T[k] * F.bg[2];
+            F.final_T[pix] = T[k];
+            F.last[pix] = last[k];
+        }
     }
 }
 
@@ -92,7 +120,8 @@ __global__ __launch_bounds__(256) void k_raster(const FrameDev* __restrict__ tab
 // reverse
 // ---------------------------------------------------------------------------
 
-// Sum over the 64 lanes of a wave; the total lands in lane 63.
+// Sum over the 64 lanes of a wave with DPP row operations; the total lands in
+// lane 63.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_add(float v)
 {
@@ -110,105 +139,125 @@ __device__ __forceinline__ float wave_sum_to_lane63(float v)
     return v;
 }
 
-__global__ __launch_bounds__(256) void k_raster_bwd(const FrameDev* __restrict__ tab, BlockMap bm,
-                                                    const uint2* __restrict__ ranges,
-                                                    const uint32_t* __restrict__ pair_g,
-                                                    const float4* __restrict__ splat,
-                                                    float* __restrict__ d_splat)
+__device__ __forceinline__ uint32_t wave_max(uint32_t v)
 {
-    __shared__ SplatLDS s;
-    __shared__ uint32_t s_g[256];
-    __shared__ uint32_t s_maxlast;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off));
+    return v;
+}
+
+// Front-to-back recomputation: for each splat up to the pixel's last
+// contributor, with S = C_out - sum_{j<=i} rgb_j w_j (the colour still to come,
+// background included):  dC/d rgb_i = w_i,  dC/d alpha_i = rgb_i T_i -
+// S_i / (1 - alpha_i).  Per lane the four pixels' terms are folded into sums
+// (S0 = sum s, S1 = sum s dy, S2 = sum s dy^2 with s = dl/d alpha * alpha)
+// from which the mean, conic and opacity derivatives follow; each of the nine
+// splat derivatives is then summed over the wave and added with one atomic.
+__global__ __launch_bounds__(64) void k_raster_bwd(const FrameDev* __restrict__ tab, BlockMap bm,
+                                                   const uint2* __restrict__ ranges,
+                                                   const uint32_t* __restrict__ pair_g,
+                                                   const float4* __restrict__ splat,
+                                                   float* __restrict__ d_splat)
+{
     const int f = frame_of_block(bm, blockIdx.x);
     const FrameDev& F = tab[f];
     const uint32_t tile = blockIdx.x - bm.start[f];
     const uint32_t tx = tile % F.tiles_x, ty = tile / F.tiles_x;
-    const uint32_t px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
-    const bool inside = px < F.W && py < F.H;
-    const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
-    const uint2 rg = ranges[F.t0 + tile];
-    const size_t g0 = F.g0, n = F.n;
-    const int lane = threadIdx.x & 63;
-
-    float Cout[3] = {0.f, 0.f, 0.f}, gC[3] = {0.f, 0.f, 0.f};
-    uint32_t last = 0;
-    if (threadIdx.x == 0) s_maxlast = 0;
-    __syncthreads();
-    if (inside) {
-        const size_t pix = (size_t)py * F.W + px, plane = (size_t)F.W * F.H;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t px = tx * kTile + (lane & 15);
+    const uint32_t py0 = ty * kTile + (lane >> 4) * 4;
+    const float fx = (float)px + 0.5f;
+    const size_t plane = (size_t)F.W * F.H;
+    float fy[4], T[4], Co[4][3], gC[4][3], acc[4][3];
+    uint32_t last[4];
+    uint32_t lmax = 0;
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            Cout[ch] = F.image[ch * plane + pix];
-            gC[ch] = F.dL_dimage[ch * plane + pix];
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t py = py0 + k;
+        fy[k] = (float)py + 0.5f;
+        T[k] = 1.0f;
+        last[k] = 0;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) Co[k][ch] = gC[k][ch] = acc[k][ch] = 0.0f;
+        if (px < F.W && py < F.H) {
+            const size_t pix = (size_t)py * F.W + px;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                Co[k][ch] = F.image[ch * plane + pix];
+                gC[k][ch] = F.dL_dimage[ch * plane + pix];
+            }
+            last[k] = F.last[pix];
         }
-        last = F.last[pix];
-        atomicMax(&s_maxlast, last);
+        lmax = max(lmax, last[k]);
     }
-    __syncthreads();
-    const uint32_t maxlast = s_maxlast;
-    float T = 1.0f, acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
-    for (uint32_t b = rg.x; b < rg.x + maxlast; b += 256) {
-        const uint32_t e = b + threadIdx.x;
-        if (e < rg.y) {
-            const uint32_t g = min(pair_g[e], F.n - 1);  // in range for well-formed pairs
-            s_g[threadIdx.x] = g;
-            stage_splat(s, threadIdx.x, splat, g0 + g);
-        }
-        __syncthreads();
-        const int cnt = (int)min(256u, rg.x + maxlast - b);
-        for (int j = 0; j < cnt; ++j) {
-            const float4 p0 = s.p0[j];
-            const float4 p1 = s.p1[j];
-            const float dx = p0.x - fpx, dy = p0.y - fpy;
-            float g_u = 0.f, g_v = 0.f, g_A = 0.f, g_B = 0.f, g_C = 0.f, g_op = 0.f;
-            float g_r = 0.f, g_g = 0.f, g_b = 0.f;
-            bool contrib = false;
-            if (b - rg.x + (uint32_t)j < last) {
-                const float power = p0.z * dx * dx + p0.w * dx * dy + p1.x * dy * dy;
-                const float G = exp2f(power);
-                const float raw = p1.y * G;
-                const float alpha = fminf(kAlphaMax, raw);
-                if (alpha >= kAlphaMin) {
-                    contrib = true;
-                    const float rgb2 = s.p2[j];
-                    const float wgt = alpha * T;
-                    acc0 += p1.z * wgt;
-                    acc1 += p1.w * wgt;
-                    acc2 += rgb2 * wgt;
-                    g_r = wgt * gC[0];
-                    g_g = wgt * gC[1];
-                    g_b = wgt * gC[2];
-                    const float inv1m = 1.0f / (1.0f - alpha);
-                    const float ga = gC[0] * (p1.z * T - (Cout[0] - acc0) * inv1m) +
-                                     gC[1] * (p1.w * T - (Cout[1] - acc1) * inv1m) +
-                                     gC[2] * (rgb2 * T - (Cout[2] - acc2) * inv1m);
-                    if (raw < kAlphaMax) {
-                        g_op = ga * G;
-                        const float gp = ga * alpha * kLn2;  // dl/d power
-                        g_u = gp * (2.f * p0.z * dx + p0.w * dy);
-                        g_v = gp * (p0.w * dx + 2.f * p1.x * dy);
-                        g_A = gp * dx * dx;
-                        g_B = gp * dx * dy;
-                        g_C = gp * dy * dy;
-                    }
-                    T = T * (1.0f - alpha);
-                }
-            }
-            if (__ballot(contrib)) {
-                float v[9] = {g_u, g_v, g_A, g_B, g_C, g_op, g_r, g_g, g_b};
-                float mine = 0.f;
+    const uint32_t maxlast = wave_max(lmax);
+    const uint2 rg = ranges[F.t0 + tile];
+    const uint32_t e_end = min(rg.y, rg.x + maxlast);
+    const float4* __restrict__ rec = splat + (size_t)F.g0 * 3;
+    const uint32_t gmax = __builtin_amdgcn_readfirstlane(F.n - 1);  // pairs exist only if n > 0
+    const size_t n = F.n, g0 = F.g0;
+    for (uint32_t e = rg.x; e < e_end; ++e) {
+        const uint32_t g = min(pair_g[e], gmax);
+        const Splat s = load_splat(rec, g);
+        const uint32_t pos = e - rg.x;
+        const float dx = s.u - fx;
+        const float base = fmaf(s.A * dx, dx, s.lo);
+        const float Bdx = s.B * dx;
+        float p[4], dyv[4];
+        bool pass[4];
 #pragma unroll
-                for (int k = 0; k < 9; ++k) {
-                    const float t = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_to_lane63(v[k])), 63));
-                    if (lane == k) mine = t;
-                }
-                // conic gradients back from the scaled (A, B, C) to (a, b, c)
-                if (lane == 2 || lane == 4) mine *= -0.5f * kLog2e;
-                if (lane == 3) mine *= -kLog2e;
-                if (lane < 9) atomicAdd(&d_splat[9 * g0 + (size_t)lane * n + s_g[j]], mine);
-            }
+        for (int k = 0; k < 4; ++k) {
+            dyv[k] = s.v - fy[k];
+            p[k] = fmaf(dyv[k], fmaf(s.C, dyv[k], Bdx), base);
+            pass[k] = pos < last[k] && p[k] >= kLog2AlphaMin;
         }
-        __syncthreads();
+        if (__ballot(pass[0] || pass[1] || pass[2] || pass[3]) == 0) continue;
+        float S0 = 0.f, S1 = 0.f, S2 = 0.f, Sr = 0.f, Sg = 0.f, Sb = 0.f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float raw = exp2_fast(p[k]);
+            const float alpha = fminf(kAlphaMax, raw);
+            const float w = T[k] * alpha;
+            const float Tn = T[k] - w;
+            const bool con = pass[k] && !(Tn < kTMin);
+            const float wc = con ? w : 0.0f;
+            acc[k][0] = fmaf(s.r, wc, acc[k][0]);
+            acc[k][1] = fmaf(s.g, wc, acc[k][1]);
+            acc[k][2] = fmaf(s.b, wc, acc[k][2]);
+            const float inv = 1.0f / (1.0f - alpha);
+            const float dot_rgb = gC[k][0] * s.r + gC[k][1] * s.g + gC[k][2] * s.b;
+            const float dot_s = gC[k][0] * (Co[k][0] - acc[k][0]) + gC[k][1] * (Co[k][1] - acc[k][1]) +
+                                gC[k][2] * (Co[k][2] - acc[k][2]);
+            const float ga = T[k] * dot_rgb - dot_s * inv;
+            const float sk = (con && raw < kAlphaMax) ? ga * alpha : 0.0f;
+            S0 += sk;
+            const float sdy = sk * dyv[k];
+            S1 += sdy;
+            S2 = fmaf(sdy, dyv[k], S2);
+            Sr = fmaf(wc, gC[k][0], Sr);
+            Sg = fmaf(wc, gC[k][1], Sg);
+            Sb = fmaf(wc, gC[k][2], Sb);
+            T[k] = con ? Tn : T[k];
+        }
+        // derivatives w.r.t. (u, v, a, b, c, opacity, r, g, b) of this lane's pixels
+        float v9[9];
+        v9[0] = kLn2 * (2.0f * s.A * dx * S0 + s.B * S1);
+        v9[1] = kLn2 * (Bdx * S0 + 2.0f * s.C * S1);
+        v9[2] = -0.5f * dx * dx * S0;
+        v9[3] = -dx * S1;
+        v9[4] = -0.5f * S2;
+        v9[5] = S0;
+        v9[6] = Sr;
+        v9[7] = Sg;
+        v9[8] = Sb;
+        float mine = 0.f;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const float t = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_to_lane63(v9[q])), 63));
+            if (lane == (uint32_t)q) mine = t;
+        }
+        if (lane == 5) mine *= exp2_fast(-s.lo);  // d alpha / d alpha_c = alpha / alpha_c
+        if (lane < 9) atomicAdd(&d_splat[9 * g0 + (size_t)lane * n + g], mine);
     }
 }
 

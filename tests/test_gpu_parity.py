@@ -79,8 +79,12 @@ def test_project_parity(R, case):
     sp = b.splat().cpu().numpy().astype(np.float64)
     np.testing.assert_allclose(sp[both, 0:2].T, pr.mean2d[:, both], rtol=2e-6, atol=2e-4)
     cscale = np.maximum(np.abs(pr.conic[0]), np.abs(pr.conic[2]))[both]
-    assert np.all(np.abs(sp[both, 2:5].T - pr.conic[:, both]) <= 2e-4 * cscale[None, :] + 1e-9)
-    np.testing.assert_allclose(sp[both, 5], sl.alpha_c[both], rtol=1e-6)
+    # the record stores the exponent coefficients -log2(e) (a/2, b, c/2) and log2(alpha_c)
+    log2e = 1.4426950408889634
+    conic = sp[both, 2:5].T / np.array([[-0.5 * log2e], [-log2e], [-0.5 * log2e]])
+    assert np.all(np.abs(conic - pr.conic[:, both]) <= 2e-4 * cscale[None, :] + 1e-9)
+    np.testing.assert_allclose(sp[both, 10], sl.alpha_c[both], rtol=1e-6)
+    np.testing.assert_allclose(2.0 ** sp[both, 5], sl.alpha_c[both], rtol=2e-6)
     np.testing.assert_allclose(sp[both, 6:9].T, pr.rgb[:, both], atol=2e-6)
     np.testing.assert_allclose(sp[both, 9], pr.depth[both], rtol=1e-6)
 
