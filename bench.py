@@ -28,12 +28,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # 256 CUs x 64 lanes x 2.4 GHz: one non-packed FP32 VALU operation per lane per clock
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# FP32 operations one (pixel, splat) test needs at minimum: dx, dy (2), the
-# quadratic form (5), exp2 (1, counted as 4: quarter rate), opacity product
-# and clamp (2), threshold test (1), transmittance update (2), stop test (1)
-OPS_PER_EVAL = 17
-# ... and per contributing (pixel, splat): weight (1) and three colour FMAs (3)
-OPS_PER_CONTRIB = 4
+# FP32 operations the compositing definition needs: every (pixel, splat) test
+# up to the pixel's last contributor takes dx, dy (2), the exponent
+# A dx^2 + B dx dy + C dy^2 + lo (5) and the threshold compare (1); every
+# contributing pair adds exp2 (counted 4: quarter rate), the 0.99 clamp,
+# w = T alpha, T' = T - w, the stop compare and three colour FMAs.
+OPS_PER_TEST = 8
+OPS_PER_CONTRIB = 11
 
 
 def parse():
@@ -181,14 +182,19 @@ def main():
     # correctness of the timed run: no frame overflowed its arena
     overflow = 0
     pairs = []
-    evals = contrib = 0
+    tests = contribs = 0
     for b in batches:
         c = R.read_counts(b)
         overflow += int(np.sum(c[:, L.SD7_CNT_FLAGS] & L.SD7_FLAG_PAIR_OVERFLOW != 0))
         pairs += [int(x) for x in c[:, L.SD7_CNT_PAIRS]]
         for fr in b.frames:
-            last = fr.last.to(torch.int64)
-            evals += int(last.sum())
+            tests += int(fr.last.to(torch.int64).sum())
+    # contributing (pixel, splat) pairs: one untimed pass with per-pixel counts
+    for b in batches:
+        fc = R.make_frames([(fr.scene, fr.view) for fr in b.frames], count=True)
+        bc = R.batch(fc, b.capacity)
+        R.stage("sd7_render", bc)
+        contribs += sum(int(fr.ncontrib.to(torch.int64).sum()) for fr in fc)
     stage_ms = {s: [] for s in stages}
     for e in ev:
         for k, s in enumerate(stages):
@@ -198,14 +204,15 @@ def main():
 
     # -- roofline of the dominant kernel (the rasterizer)
     t_r = stage_avg["sd7_rasterize"] * 1e-3                        # per batch launch, s
-    ev_per_launch = evals / len(batches)
-    ops = ev_per_launch * OPS_PER_EVAL
+    tests_l, contribs_l = tests / len(batches), contribs / len(batches)
+    ops = tests_l * OPS_PER_TEST + contribs_l * OPS_PER_CONTRIB
     achieved = ops / t_r / 1e12
     roofline = {"bound": "alu", "kernel": "k_raster", "achieved": round(achieved, 3),
                 "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
                 "traffic": None,
-                "algorithmic_units": "(pixel, splat) tests up to each pixel's last contributor",
-                "ops_per_unit": OPS_PER_EVAL, "units_per_launch": int(ev_per_launch),
+                "algorithmic_units": {"tests_per_launch": int(tests_l), "ops_per_test": OPS_PER_TEST,
+                                      "contribs_per_launch": int(contribs_l),
+                                      "ops_per_contrib": OPS_PER_CONTRIB},
                 "avg_launch_ms": round(stage_avg["sd7_rasterize"], 4)}
 
     # -- latency: batched (frames of a batch finish with their batch) vs plain

@@ -151,6 +151,8 @@ typedef struct {
     uint32_t* last;          /* out [H][W]: tile-list entries up to the last contributor */
     const float* dL_dimage;  /* in  [3][H][W]: backward only (may be NULL otherwise) */
     sd7_scene_grad grad;     /* out: backward only (may be NULL otherwise) */
+    uint32_t* ncontrib;      /* optional out [H][W]: splats that contributed to the pixel;
+                                NULL: not counted (the count costs one add per test) */
 } sd7_frame;
 
 /* Workspace layout.  Every offset is in bytes from the workspace base and a
@@ -171,11 +173,14 @@ typedef struct {
  *   off_depth_key uint32 [Ntot]                float bits of depth; 0xFFFFFFFF = culled
  *   off_order    uint32 [Ntot]                 frame-local indices of kept Gaussians in
  *                                              (depth, index) order; entries >= kept unused
- *   off_pair_tile, off_pair_g  uint32 [capacity]  sorted pairs: tile id (frame-local,
- *                                              ty*tiles_x+tx) and frame-local Gaussian index;
- *                                              frame f at arena slot counts[f][SD7_CNT_PAIR_BASE]
- *   off_ranges   uint32 [Ttot][2]              per tile [begin, end) arena slots; frame f's
- *                                              tiles start at the running sum of its tile counts
+ *   off_pair_g   uint32 [capacity]             the pair arena: frame-local Gaussian index of
+ *                                              every (tile, Gaussian) pair, grouped by tile
+ *                                              (row-major tile ids ty*tiles_x+tx) and in
+ *                                              (depth, index) order within a tile; frame f
+ *                                              from arena slot counts[f][SD7_CNT_PAIR_BASE]
+ *   off_ranges   uint32 [Ttot][2]              per tile [begin, end) arena slots (the tile of
+ *                                              slot i is the tile whose range holds i); frame
+ *                                              f's tiles start at the running sum of tile counts
  *   off_d_splat  float  [9 planes]             backward: dL/d(u, v, a, b, c, opacity, r, g, b)
  *   off_d_mu_c, off_d_cov_c, off_d_alpha_c     backward: dL/d of the slice outputs
  */
@@ -191,7 +196,7 @@ typedef struct {
     size_t off_mu_c, off_cov_c, off_alpha_c;
     size_t off_splat, off_rect, off_depth_key;
     size_t off_order;
-    size_t off_pair_tile, off_pair_g;
+    size_t off_pair_g;
     size_t off_ranges;
     size_t off_d_splat, off_d_mu_c, off_d_cov_c, off_d_alpha_c;
     size_t off_scratch; /* sort and scan temporaries; no stable meaning */
@@ -223,9 +228,13 @@ sd7_status sd7_slice(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t pair
 /* Sec. 4.4 projection: writes splat, rect, depth_key and the KEPT counters. */
 sd7_status sd7_project(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t pair_capacity,
                        void* ws, size_t ws_bytes, sd7_stream stream);
-/* Depth sort, pair emission, tile sort, tile ranges: writes order, pair_tile,
+/* Depth sort of the kept Gaussians, then the tile lists: writes order,
  * pair_g, ranges and the PAIRS / PAIR_BASE counters; sets
- * SD7_FLAG_PAIR_OVERFLOW for frames whose pairs do not fit. */
+ * SD7_FLAG_PAIR_OVERFLOW for frames whose pairs do not fit.  Tile lists are
+ * built by counting (per chunk of depth-sorted Gaussians, how many boxes cover
+ * each tile) and placement; calls with a frame of more than 16384 tiles use a
+ * stable radix sort of (tile, Gaussian) pairs instead.  Both give the same
+ * arena contents. */
 sd7_status sd7_bin(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t pair_capacity,
                    void* ws, size_t ws_bytes, sd7_stream stream);
 /* Front-to-back compositing into each frame's image, final_T and last. */

@@ -38,11 +38,11 @@ class Sd7SceneGrad(ctypes.Structure):
 
 class Sd7Frame(ctypes.Structure):
     _fields_ = [("scene", Sd7Scene), ("view", Sd7View), ("image", P), ("final_T", P),
-                ("last", P), ("dL_dimage", P), ("grad", Sd7SceneGrad)]
+                ("last", P), ("dL_dimage", P), ("grad", Sd7SceneGrad), ("ncontrib", P)]
 
 
 _OFFS = ["off_table", "off_counts", "off_mu_c", "off_cov_c", "off_alpha_c", "off_splat",
-         "off_rect", "off_depth_key", "off_order", "off_pair_tile", "off_pair_g", "off_ranges",
+         "off_rect", "off_depth_key", "off_order", "off_pair_g", "off_ranges",
          "off_d_splat", "off_d_mu_c", "off_d_cov_c", "off_d_alpha_c", "off_scratch"]
 
 

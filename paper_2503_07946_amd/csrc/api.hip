@@ -53,8 +53,9 @@ uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); 
 // Offsets of the scratch sub-arrays (inside off_scratch .. bytes).
 struct Scratch {
     size_t sk_a, sv_a, sk_b;         // depth sort ping-pong (keys a, vals a, keys b)
-    size_t pt_b, pg_b;               // pair ping-pong buffers
+    size_t pt_a, pt_b, pg_b;         // radix tile sort: tile keys and ping-pong buffers
     size_t toff;                     // tile offsets (scan of tiles per sorted Gaussian)
+    size_t srect;                    // tile boxes in depth order (counting binner)
     size_t segs_all, segs_kept, segs_pairs;
     size_t tot_all, tot_kept, tot_pairs;
     size_t hist, partials, words;
@@ -68,7 +69,35 @@ struct Plan {
     BlockMap gmap;   // blocks of 256 Gaussians per frame
     BlockMap tmap;   // one block per tile
     uint32_t gblocks, tblocks;
+    // counting binner (frames of at most kMaxCountTiles tiles)
+    bool counting;
+    uint32_t max_tiles;
+    uint32_t nch[SD7_MAX_FRAMES], m0[SD7_MAX_FRAMES];
+    BlockMap cmap;   // one block (wave) per (frame, chunk, tile group)
+    BlockMap kmap;   // one block per (frame, chunk)
+    uint32_t kblocks;
+    BlockMap rmap;   // blocks of 256 tiles per frame
+    uint32_t cblocks, rblocks;
+    size_t matrix_entries;
+    size_t cnt;      // workspace offset of the count matrix
+    size_t ttot;     // workspace offset of the per-tile totals (then their scan)
 };
+
+constexpr uint64_t kBinWaves = 32768;  // (chunk, group) waves the counting binner aims for per call
+constexpr uint64_t kMaxChunks = 128;   // chunks per frame (the depth of the per-tile column scan)
+constexpr size_t kMaxMatrix = (size_t)1 << 28;  // count-matrix entries of one call
+
+// Binning chunks per frame: enough (chunk, group) waves over the call to fill
+// the chip, at most kMaxChunks, and no more than one per 256 Gaussians.  The
+// kernels cut the kept Gaussians (a count known on the device) into this many
+// chunks.
+uint32_t chunk_count(int64_t n, uint32_t groups, int nf)
+{
+    if (n <= 0) return 0;
+    const uint64_t per = (uint64_t)nf * groups;
+    uint64_t nch = std::min<uint64_t>(std::max<uint64_t>(1, (kBinWaves + per - 1) / per), kMaxChunks);
+    return (uint32_t)std::min<uint64_t>(nch, ((uint64_t)n + 255) / 256);
+}
 
 sd7_status make_plan(const sd7_frame* fr, int nf, int64_t cap, Plan& P, bool need_bwd)
 {
@@ -109,9 +138,25 @@ sd7_status make_plan(const sd7_frame* fr, int nf, int64_t cap, Plan& P, bool nee
         ttot += (int64_t)tx * ty;
         max_tiles = std::max(max_tiles, tx * ty);
         wt_depth += ceil_div(n, kSortItems);
+        const uint32_t groups = ceil_div(tx, kGroup) * ceil_div(ty, kGroup);
+        P.nch[f] = chunk_count(n, groups, nf);
+        P.m0[f] = (uint32_t)std::min<size_t>(P.matrix_entries, UINT32_MAX);
+        P.cmap.start[f] = P.cblocks;
+        P.kmap.start[f] = P.kblocks;
+        P.rmap.start[f] = P.rblocks;
+        P.kblocks += P.nch[f];
+        P.cblocks += P.nch[f] * groups;
+        P.rblocks += ceil_div(tx * ty, 256);
+        P.matrix_entries += (size_t)P.nch[f] * tx * ty;
     }
     P.gmap.start[nf] = P.gblocks;
     P.tmap.start[nf] = P.tblocks;
+    P.cmap.start[nf] = P.cblocks;
+    P.kmap.start[nf] = P.kblocks;
+    P.rmap.start[nf] = P.rblocks;
+    P.cmap.nf = P.kmap.nf = P.rmap.nf = nf;
+    P.max_tiles = max_tiles;
+    P.counting = max_tiles <= kMaxCountTiles && P.matrix_entries <= kMaxMatrix;
     if (ntot >= (int64_t)1 << 31) return fail(SD7_EINVAL, "total Gaussians %lld >= 2^31", (long long)ntot);
     if (ttot >= (int64_t)1 << 31) return fail(SD7_EINVAL, "total tiles %lld >= 2^31", (long long)ttot);
     if (cap + (int64_t)nf * kSortItems >= (int64_t)1 << 31) return fail(SD7_EINVAL, "pair capacity too large");
@@ -135,7 +180,6 @@ sd7_status make_plan(const sd7_frame* fr, int nf, int64_t cap, Plan& P, bool nee
     L.off_rect = take(8 * N);
     L.off_depth_key = take(4 * N);
     L.off_order = take(4 * N);
-    L.off_pair_tile = take(4 * C);
     L.off_pair_g = take(4 * C);
     L.off_ranges = take(8 * T);
     L.off_d_splat = take(4 * 9 * N);
@@ -147,18 +191,25 @@ sd7_status make_plan(const sd7_frame* fr, int nf, int64_t cap, Plan& P, bool nee
     S.sk_a = take(4 * N);
     S.sv_a = take(4 * N);
     S.sk_b = take(4 * N);
-    S.pt_b = take(4 * C);
-    S.pg_b = take(4 * C);
+    // tile keys and ping-pong buffers of the radix tile sort (fallback binner)
+    const size_t CR = P.counting ? 0 : C;
+    S.pt_a = take(4 * CR);
+    S.pt_b = take(4 * CR);
+    S.pg_b = take(4 * CR);
     S.toff = take(4 * (N + 16));
+    S.srect = take(8 * (P.counting ? N : 0));
     S.segs_all = take(sizeof(SortSeg) * nf);
     S.segs_kept = take(sizeof(SortSeg) * nf);
     S.segs_pairs = take(sizeof(SortSeg) * nf);
     S.tot_all = take(sizeof(SortTotals));
     S.tot_kept = take(sizeof(SortTotals));
     S.tot_pairs = take(sizeof(SortTotals));
-    P.hist_entries = 256 * (size_t)std::max(P.max_wt_depth, P.max_wt_pairs);
+    P.hist_entries = 256 * (size_t)std::max(P.max_wt_depth, P.counting ? 0u : P.max_wt_pairs);
     S.hist = take(4 * P.hist_entries);
-    P.partial_entries = std::max(P.hist_entries, N) / kScanItems + 4;
+    const size_t mat = P.counting ? P.matrix_entries : 0;
+    P.cnt = take(4 * mat);
+    P.ttot = take(4 * (P.counting ? T + 4 : 0));
+    P.partial_entries = std::max(std::max(P.hist_entries, N), mat) / kScanItems + 4;
     S.partials = take(4 * P.partial_entries);
     S.words = take(4 * 64);
     L.bytes = off;
@@ -196,6 +247,7 @@ sd7_status upload_table(sd7_ctx* ctx, const sd7_frame* fr, int nf, const Plan& P
         D.image = F.image; D.final_T = F.final_T; D.last = F.last; D.dL_dimage = F.dL_dimage;
         D.g_mu_p = F.grad.mu_p; D.g_mu_t = F.grad.mu_t; D.g_mu_d = F.grad.mu_d;
         D.g_L = F.grad.L; D.g_alpha = F.grad.alpha; D.g_sh = F.grad.sh;
+        D.ncontrib = F.ncontrib;
         D.n = (uint32_t)F.scene.n;
         D.g0 = (uint32_t)P.L.g0[f];
         D.W = (uint32_t)F.view.W;
@@ -203,6 +255,8 @@ sd7_status upload_table(sd7_ctx* ctx, const sd7_frame* fr, int nf, const Plan& P
         D.tiles_x = ceil_div(D.W, kTile);
         D.tiles_y = ceil_div(D.H, kTile);
         D.t0 = (uint32_t)P.L.tile0[f];
+        D.nch = P.nch[f];
+        D.m0 = P.m0[f];
         std::memcpy(D.R, F.view.R_wc, sizeof(D.R));
         std::memcpy(D.c, F.view.c, sizeof(D.c));
         D.fx = F.view.fx; D.fy = F.view.fy; D.cx = F.view.cx; D.cy = F.view.cy;
@@ -223,6 +277,7 @@ struct Call {
     hipStream_t st;
     const FrameDev* tab;
     uint32_t* counts;
+    bool count;  // some frame asks for per-pixel contributor counts
     template <class T>
     T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
@@ -243,6 +298,8 @@ sd7_status begin(sd7_ctx* ctx, const sd7_frame* fr, int nf, int64_t cap, void* w
     c.st = static_cast<hipStream_t>(stream);
     c.tab = c.at<FrameDev>(c.P.L.off_table);
     c.counts = c.at<uint32_t>(c.P.L.off_counts);
+    c.count = false;
+    for (int f = 0; f < nf; ++f) c.count = c.count || fr[f].ncontrib != nullptr;
     return upload_table(ctx, fr, nf, c.P, c.ws, c.st);
 }
 
@@ -341,7 +398,8 @@ sd7_status do_bin(const Call& c)
     uint32_t* toff = c.at<uint32_t>(S.toff);
     if (c.P.gblocks) {
         k_gather_ntiles<<<c.P.gblocks, kBlock, 0, c.st>>>(c.tab, c.P.gmap, c.counts, order,
-                                                          c.at<uint2>(L.off_rect), toff);
+                                                          c.at<uint2>(L.off_rect), toff,
+                                                          c.P.counting ? c.at<uint2>(S.srect) : nullptr);
         LAUNCH_CHECK("k_gather_ntiles");
     }
     const uint32_t ntot = (uint32_t)L.n_total;
@@ -350,9 +408,33 @@ sd7_status do_bin(const Call& c)
     k_setup_pairs<<<1, 64, 0, c.st>>>(c.tab, nf, ntot, toff, words, (uint32_t)L.pair_capacity, c.counts,
                                       segs_pairs, tot_pairs);
     LAUNCH_CHECK("k_setup_pairs");
+    if (c.P.counting) {
+        // counting binner: [chunk][tile] counts -> per-tile prefix over chunks and
+        // tile totals -> scan of the totals -> placement -> ranges
+        uint32_t* cnt = c.at<uint32_t>(c.P.cnt);
+        uint32_t* ttot = c.at<uint32_t>(c.P.ttot);
+        const uint2* srect = c.at<uint2>(S.srect);
+        const uint32_t ttiles = (uint32_t)L.tiles_total;
+        if (c.P.kblocks) {
+            k_tile_count<<<c.P.kblocks, 256, sizeof(uint32_t) * c.P.max_tiles, c.st>>>(c.tab, c.P.kmap, c.counts,
+                                                                                      srect, cnt);
+            LAUNCH_CHECK("k_tile_count");
+        }
+        k_tile_colscan<<<c.P.rblocks, 256, 0, c.st>>>(c.tab, c.P.rmap, cnt, ttot);
+        LAUNCH_CHECK("k_tile_colscan");
+        if ((s = scan(c, ttot, ttiles, nullptr, ttiles, nullptr)) != SD7_OK) return s;
+        if (c.P.cblocks) {
+            k_group_place<<<c.P.cblocks, 64, 0, c.st>>>(c.tab, c.P.cmap, c.counts, order, srect, cnt, ttot,
+                                                         c.at<uint32_t>(L.off_pair_g));
+            LAUNCH_CHECK("k_group_place");
+        }
+        k_tile_ranges<<<c.P.rblocks, 256, 0, c.st>>>(c.tab, c.P.rmap, c.counts, ttot, c.at<uint2>(L.off_ranges));
+        LAUNCH_CHECK("k_tile_ranges");
+        return SD7_OK;
+    }
     if ((s = fill(c, c.at<uint32_t>(L.off_ranges), 2 * (size_t)L.tiles_total, 0)) != SD7_OK) return s;
-    // emit so that the last tile-sort pass lands in the pair_tile/pair_g arrays
-    uint32_t* pt_a = c.at<uint32_t>(L.off_pair_tile);
+    // emit so that the last tile-sort pass lands in the pair_g array
+    uint32_t* pt_a = c.at<uint32_t>(S.pt_a);
     uint32_t* pg_a = c.at<uint32_t>(L.off_pair_g);
     uint32_t* pt_b = c.at<uint32_t>(S.pt_b);
     uint32_t* pg_b = c.at<uint32_t>(S.pg_b);
@@ -379,8 +461,12 @@ sd7_status do_bin(const Call& c)
 sd7_status do_raster(const Call& c)
 {
     const sd7_layout& L = c.P.L;
-    k_raster<<<c.P.tblocks, 64, 0, c.st>>>(c.tab, c.P.tmap, c.at<uint2>(L.off_ranges), c.at<uint32_t>(L.off_pair_g),
-                                             c.at<float4>(L.off_splat));
+    if (c.count)
+        k_raster<true><<<c.P.tblocks, 64, 0, c.st>>>(c.tab, c.P.tmap, c.at<uint2>(L.off_ranges),
+                                                     c.at<uint32_t>(L.off_pair_g), c.at<float4>(L.off_splat));
+    else
+        k_raster<false><<<c.P.tblocks, 64, 0, c.st>>>(c.tab, c.P.tmap, c.at<uint2>(L.off_ranges),
+                                                      c.at<uint32_t>(L.off_pair_g), c.at<float4>(L.off_splat));
     LAUNCH_CHECK("k_raster");
     return SD7_OK;
 }
@@ -438,6 +524,10 @@ sd7_status sd7_create(int device, sd7_ctx** out)
     HIP_TRY(hipGetDeviceCount(&count));
     if (device < 0 || device >= count) return fail(SD7_EINVAL, "device %d outside [0, %d)", device, count);
     HIP_TRY(hipSetDevice(device));
+    // k_tile_count keeps one counter per tile of a frame in LDS (up to 128 KB)
+    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tile_count),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(sizeof(uint32_t) * kMaxCountTiles)));
     sd7_ctx* c = new (std::nothrow) sd7_ctx();
     if (!c) return fail(SD7_ENOMEM, "out of host memory");
     c->device = device;

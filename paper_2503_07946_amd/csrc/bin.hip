@@ -304,12 +304,15 @@ __global__ void k_setup_depth(const FrameDev* __restrict__ tab, int nf, const ui
     tot_kept->wt = wt_kept; tot_kept->hist_len = 256u * wt_kept;
 }
 
-// Tiles touched by each Gaussian in depth order (0 past the kept ones).
+// Tiles touched by each Gaussian in depth order (0 past the kept ones) and,
+// when srect is given, the tile boxes themselves in depth order (empty boxes
+// past the kept ones).
 __global__ __launch_bounds__(kBlock) void k_gather_ntiles(const FrameDev* __restrict__ tab, BlockMap bm,
                                                           const uint32_t* __restrict__ counts,
                                                           const uint32_t* __restrict__ order,
                                                           const uint2* __restrict__ rect,
-                                                          uint32_t* __restrict__ ntiles)
+                                                          uint32_t* __restrict__ ntiles,
+                                                          uint2* __restrict__ srect)
 {
     const int f = frame_of_block(bm, blockIdx.x);
     const FrameDev& F = tab[f];
@@ -317,11 +320,13 @@ __global__ __launch_bounds__(kBlock) void k_gather_ntiles(const FrameDev* __rest
     if (j >= F.n) return;
     const uint32_t kept = counts[f * SD7_CNT_WORDS + SD7_CNT_KEPT];
     uint32_t nt = 0;
+    uint2 r = make_uint2(0u, 0u);
     if (j < kept) {
-        const uint2 r = rect[F.g0 + order[F.g0 + j]];
+        r = rect[F.g0 + order[F.g0 + j]];
         nt = ((r.y & 0xFFFFu) - (r.x & 0xFFFFu)) * ((r.y >> 16) - (r.x >> 16));
     }
     ntiles[F.g0 + j] = nt;
+    if (srect) srect[F.g0 + j] = r;
 }
 
 // Per-frame pair counts, arena slots (each frame's share rounded up to a whole
@@ -448,6 +453,221 @@ __global__ __launch_bounds__(256) void k_ranges(const FrameDev* __restrict__ tab
             if (e + 1 == sg.len || pair_tile[i + 1] != t) ranges[t0 + t].y = i + 1;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// counting binner: tile lists straight from the depth-sorted tile boxes
+//
+// The kept Gaussians of a frame, in depth order, are cut into nch chunks.
+// k_tile_count writes how many of each chunk's boxes cover each tile into a
+// [chunk][tile] matrix; a per-tile exclusive prefix over the chunks and a
+// scan of the tile totals give every (chunk, tile) run its first arena slot,
+// so the runs of one tile follow each other in depth order.  k_group_place
+// then runs one wave per (chunk, group of 8 x 8 tiles), one lane per tile: it
+// scans the chunk's boxes in depth order, visits those that meet the group
+// one at a time, and every lane whose tile the box covers appends the
+// Gaussian to its run.  Each tile list thus comes out in (depth, index) order
+// without a sort over pairs, and every wave writes only its own 64 runs.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t frame_kept(const uint32_t* counts, int f)
+{
+    return counts[f * SD7_CNT_WORDS + SD7_CNT_KEPT];
+}
+
+// First depth-sorted Gaussian of chunk c when kept Gaussians are cut into
+// nch chunks of equal size (multiples of 64, the last one shorter).
+__device__ __forceinline__ uint32_t chunk_begin(uint32_t kept, uint32_t nch, uint32_t c)
+{
+    const uint32_t len = ((kept + nch - 1) / nch + 63) & ~63u;
+    return min(kept, c * len);
+}
+
+// Boxes a counting-binner wave loads ahead of the one it is working on.
+constexpr int kBinAhead = 4;
+
+// One block (256 lanes) per (frame, chunk) writes the chunk's row of the
+// count matrix (zeros for a frame whose pairs overflowed).  Per-row difference
+// array over the frame's tiles in LDS: a box [x0, x1) x [y0, y1) adds +1 at
+// (x0, y) and -1 at (x1, y) of each of its rows.
+__global__ __launch_bounds__(256) void k_tile_count(const FrameDev* __restrict__ tab, BlockMap cm,
+                                                    const uint32_t* __restrict__ counts,
+                                                    const uint2* __restrict__ srect,
+                                                    uint32_t* __restrict__ cnt)
+{
+    extern __shared__ uint32_t s_d[];
+    const int f = frame_of_block(cm, blockIdx.x);
+    const FrameDev& F = tab[f];
+    const uint32_t c = blockIdx.x - cm.start[f];
+    const uint32_t tx = F.tiles_x, T = F.tiles_x * F.tiles_y;
+    for (uint32_t i = threadIdx.x; i < T; i += 256) s_d[i] = 0;
+    __syncthreads();
+    const uint32_t* cf = counts + f * SD7_CNT_WORDS;
+    const bool live = !(cf[SD7_CNT_FLAGS] & SD7_FLAG_PAIR_OVERFLOW);
+    const uint32_t kept = frame_kept(counts, f);
+    const uint32_t j0 = chunk_begin(kept, F.nch, c), j1 = chunk_begin(kept, F.nch, c + 1);
+    if (live) {
+        for (uint32_t j = j0 + threadIdx.x; j < j1; j += 256) {
+            const uint2 r = srect[F.g0 + j];
+            const uint32_t x0 = r.x & 0xFFFFu, y0 = r.x >> 16, x1 = r.y & 0xFFFFu, y1 = r.y >> 16;
+            for (uint32_t y = y0; y < y1; ++y) {
+                atomicAdd(&s_d[y * tx + x0], 1u);
+                if (x1 < tx) atomicSub(&s_d[y * tx + x1], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t y = threadIdx.x; y < F.tiles_y; y += 256) {
+        uint32_t run = 0;
+        for (uint32_t x = 0; x < tx; ++x) {
+            run += s_d[y * tx + x];
+            s_d[y * tx + x] = run;
+        }
+    }
+    __syncthreads();
+    uint32_t* row = cnt + F.m0 + (size_t)c * T;
+    for (uint32_t t = threadIdx.x; t < T; t += 256) row[t] = s_d[t];
+}
+
+// One wave per (frame, chunk, group of kGroup x kGroup tiles), one lane per
+// tile of the group: appends the chunk's Gaussians, in depth order, to the
+// runs of the group's tiles, starting at the slots the scans gave.  Logical
+// block b of a frame is chunk b / groups, group b % groups, and logical
+// blocks are laid out contiguously per XCD, so the groups of one chunk run
+// side by side on one XCD and share its boxes in that XCD's L2.
+__global__ __launch_bounds__(64) void k_group_place(const FrameDev* __restrict__ tab, BlockMap cm,
+                                                    const uint32_t* __restrict__ counts,
+                                                    const uint32_t* __restrict__ order,
+                                                    const uint2* __restrict__ srect,
+                                                    const uint32_t* __restrict__ cnt_pre,
+                                                    const uint32_t* __restrict__ tstart,
+                                                    uint32_t* __restrict__ pair_g)
+{
+    const uint32_t lb = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int f = frame_of_block(cm, lb);
+    const FrameDev& F = tab[f];
+    const uint32_t b = lb - cm.start[f];
+    const uint32_t tx = F.tiles_x, ty = F.tiles_y, T = tx * ty;
+    const uint32_t gxn = (tx + kGroup - 1) / kGroup;
+    const uint32_t ngr = gxn * ((ty + kGroup - 1) / kGroup);
+    const uint32_t c = b / ngr, gr = b - c * ngr;
+    const uint32_t bx0 = (gr % gxn) * kGroup, by0 = (gr / gxn) * kGroup;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t lx = bx0 + (lane % kGroup), ly = by0 + (lane / kGroup);
+    const bool valid = lx < tx && ly < ty;
+    const uint32_t t = ly * tx + lx;
+    const uint32_t* cf = counts + f * SD7_CNT_WORDS;
+    const uint32_t kept = cf[SD7_CNT_KEPT];
+    const uint32_t j0 = chunk_begin(kept, F.nch, c), j1 = chunk_begin(kept, F.nch, c + 1);
+    if (cf[SD7_CNT_PAIRS] == 0 || j0 >= j1) return;  // uniform over the wave
+    uint32_t slot = 0;  // next arena slot of the lane's tile
+    {
+        const uint32_t* ts = tstart + F.t0;
+        if (valid) slot = cf[SD7_CNT_PAIR_BASE] + (ts[t] - ts[0]) + cnt_pre[F.m0 + (size_t)c * T + t];
+    }
+    const uint2* rf = srect + F.g0;
+    const uint32_t* of = order + F.g0;
+    // the boxes and indices of the next kBinAhead x 64 Gaussians are loaded
+    // while the current ones are visited; empty boxes past j1
+    uint2 rn[kBinAhead];
+    uint32_t gn[kBinAhead];
+#pragma unroll
+    for (int k = 0; k < kBinAhead; ++k) {
+        const uint32_t jj = j0 + k * 64 + lane;
+        rn[k] = make_uint2(0u, 0u);
+        gn[k] = 0;
+        if (jj < j1) {
+            rn[k] = rf[jj];
+            gn[k] = of[jj];
+        }
+    }
+    for (uint32_t j = j0; j < j1; j += kBinAhead * 64) {
+        uint2 r[kBinAhead];
+        uint32_t g[kBinAhead];
+#pragma unroll
+        for (int k = 0; k < kBinAhead; ++k) {
+            r[k] = rn[k];
+            g[k] = gn[k];
+            const uint32_t jj = j + (kBinAhead + k) * 64 + lane;
+            rn[k] = make_uint2(0u, 0u);
+            if (jj < j1) {
+                rn[k] = rf[jj];
+                gn[k] = of[jj];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kBinAhead; ++k) {
+            const uint32_t x0 = r[k].x & 0xFFFFu, y0 = r[k].x >> 16;
+            const uint32_t x1 = r[k].y & 0xFFFFu, y1 = r[k].y >> 16;
+            const bool meets = x0 < bx0 + kGroup && x1 > bx0 && y0 < by0 + kGroup && y1 > by0;
+            uint64_t m = __ballot(meets);
+            while (m) {  // the meeting boxes in depth order
+                const int p = __builtin_ctzll(m);
+                m &= m - 1;
+                const uint32_t rx = __builtin_amdgcn_readlane(r[k].x, p);
+                const uint32_t ry = __builtin_amdgcn_readlane(r[k].y, p);
+                const uint32_t gp = __builtin_amdgcn_readlane(g[k], p);
+                const uint32_t qx0 = rx & 0xFFFFu, qy0 = rx >> 16;
+                const bool hit = valid && (lx - qx0) < ((ry & 0xFFFFu) - qx0) && (ly - qy0) < ((ry >> 16) - qy0);
+                if (hit) pair_g[slot++] = gp;
+            }
+        }
+    }
+}
+
+// Per tile, exclusive prefix over the chunks (in place) and the tile's total.
+// One lane per (frame, tile); rows are read coalesced, eight at a time.
+__global__ __launch_bounds__(256) void k_tile_colscan(const FrameDev* __restrict__ tab, BlockMap tm,
+                                                      uint32_t* __restrict__ cnt, uint32_t* __restrict__ ttot)
+{
+    const int f = frame_of_block(tm, blockIdx.x);
+    const FrameDev& F = tab[f];
+    const uint32_t t = (blockIdx.x - tm.start[f]) * 256 + threadIdx.x;
+    const uint32_t T = F.tiles_x * F.tiles_y;
+    if (t >= T) return;
+    uint32_t* p = cnt + F.m0 + t;
+    const uint32_t nch = F.nch;
+    uint32_t run = 0, c = 0;
+    for (; c + 8 <= nch; c += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = p[(size_t)(c + k) * T];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            p[(size_t)(c + k) * T] = run;
+            run += v[k];
+        }
+    }
+    for (; c < nch; ++c) {
+        const uint32_t v = p[(size_t)c * T];
+        p[(size_t)c * T] = run;
+        run += v;
+    }
+    ttot[F.t0 + t] = run;
+}
+
+// Tile ranges from the scanned tile totals: tile t of frame f starts after
+// the pairs of tiles 0 .. t-1 and ends where tile t + 1 starts (the last tile
+// at the frame's pair count).
+__global__ __launch_bounds__(256) void k_tile_ranges(const FrameDev* __restrict__ tab, BlockMap tm,
+                                                     const uint32_t* __restrict__ counts,
+                                                     const uint32_t* __restrict__ tstart,
+                                                     uint2* __restrict__ ranges)
+{
+    const int f = frame_of_block(tm, blockIdx.x);
+    const FrameDev& F = tab[f];
+    const uint32_t t = (blockIdx.x - tm.start[f]) * 256 + threadIdx.x;
+    const uint32_t T = F.tiles_x * F.tiles_y;
+    if (t >= T) return;
+    const uint32_t* cf = counts + f * SD7_CNT_WORDS;
+    const uint32_t P = cf[SD7_CNT_PAIRS], pb = cf[SD7_CNT_PAIR_BASE];
+    uint2 r = make_uint2(0u, 0u);
+    if (P > 0) {
+        const uint32_t* ts = tstart + F.t0;
+        r.x = pb + ts[t] - ts[0];
+        r.y = (t + 1 < T) ? pb + ts[t + 1] - ts[0] : pb + P;
+    }
+    ranges[F.t0 + t] = r;
 }
 
 }  // namespace sd7

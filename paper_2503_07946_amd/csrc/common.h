@@ -45,12 +45,15 @@ struct FrameDev {
     float* g_L;
     float* g_alpha;
     float* g_sh;
+    uint32_t* ncontrib;  // optional per-pixel contributor count
     uint32_t n;        // Gaussians
     uint32_t g0;       // first Gaussian in the concatenated per-Gaussian arrays
     uint32_t W, H;
     uint32_t tiles_x, tiles_y;
     uint32_t t0;       // first tile in the concatenated tile arrays
+    uint32_t nch;      // binning chunks (the kept Gaussians are cut into this many)
     uint32_t pad0;
+    uint32_t m0;       // first entry of the frame's [chunk][tile] count matrix
     float R[9];
     float c[3];
     float fx, fy, cx, cy;
@@ -58,8 +61,11 @@ struct FrameDev {
     float d[3];
     float lambda_t, lambda_d;
     float bg[3];
-    float pad1[3];
+    float pad1[2];
 };
+
+constexpr uint32_t kMaxCountTiles = 32768;  // tiles per frame the counting binner takes (more: radix binner)
+constexpr uint32_t kGroup = 8;              // tiles per side of a counting-binner group (one lane per tile)
 
 // Prefix of launch blocks over the frames of a call (kernel argument).
 struct BlockMap {
@@ -103,6 +109,17 @@ __device__ __forceinline__ int seg_of_tile(const SortSeg* segs, int nseg, uint32
         if (segs[mid].wt0 <= w) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+// Workgroups of a launch go to the 8 XCDs round-robin in launch order.  This
+// maps launch index i (of nb) to a logical index such that every XCD runs one
+// contiguous range of logical blocks, whose shared data then stays in that
+// XCD's L2.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t i, uint32_t nb)
+{
+    const uint32_t x = i % kXcds, k = i / kXcds, q = nb / kXcds, rem = nb % kXcds;
+    return x * q + min(x, rem) + k;
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt()

@@ -37,6 +37,7 @@ __device__ __forceinline__ Splat load_splat(const float4* __restrict__ rec, uint
 
 __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 
+template <bool COUNT>
 __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab, BlockMap bm,
                                                const uint2* __restrict__ ranges,
                                                const uint32_t* __restrict__ pair_g,
@@ -54,13 +55,14 @@ __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab,
     // to kFar: its exponent becomes -inf there (C < 0), so it never passes the
     // opacity test again and needs no flag of its own.
     float fy[4], T[4], C0[4], C1[4], C2[4];
-    uint32_t last[4];
+    uint32_t last[4], ncon[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         fy[k] = (px < F.W && py0 + k < F.H) ? (float)(py0 + k) + 0.5f : kFar;
         T[k] = 1.0f;
         C0[k] = C1[k] = C2[k] = 0.0f;
         last[k] = 0;
+        ncon[k] = 0;
     }
     const uint2 rg = ranges[F.t0 + tile];
     const float4* __restrict__ rec = splat + (size_t)F.g0 * 3;
@@ -97,6 +99,7 @@ __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab,
                 C2[k] = fmaf(s.b, wc, C2[k]);
                 T[k] = con ? Tn : T[k];
                 last[k] = con ? pos : last[k];
+                if (COUNT) ncon[k] += con ? 1u : 0u;
                 fy[k] = (pass && sat) ? kFar : fy[k];
             }
         }
@@ -112,6 +115,7 @@ __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab,
             F.image[2 * plane + pix] = C2[k] + T[k] * F.bg[2];
             F.final_T[pix] = T[k];
             F.last[pix] = last[k];
+            if (COUNT && F.ncontrib) F.ncontrib[pix] = ncon[k];
         }
     }
 }

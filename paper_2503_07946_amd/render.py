@@ -74,6 +74,7 @@ class FrameIO:
     last: torch.Tensor
     dL_dimage: torch.Tensor | None = None
     grads: dict | None = None
+    ncontrib: torch.Tensor | None = None
 
 
 @dataclass
@@ -131,10 +132,14 @@ class Batch:
             self.nf, L.SD7_CNT_WORDS)
 
     def pairs(self, f=0, counts=None):
+        """(tile id, Gaussian index) of every pair of frame f, in arena order,
+        and the frame's first arena slot.  Tile ids come from the ranges."""
         c = self.counts().cpu().numpy() if counts is None else counts
         base, P = int(c[f, L.SD7_CNT_PAIR_BASE]), int(c[f, L.SD7_CNT_PAIRS])
-        t = self._arr(self.layout.off_pair_tile, torch.int32, P, base)
         g = self._arr(self.layout.off_pair_g, torch.int32, P, base)
+        rg = self.ranges(f).to(torch.int64)
+        lens = (rg[:, 1] - rg[:, 0]).clamp(min=0)
+        t = torch.repeat_interleave(torch.arange(rg.shape[0], device=rg.device, dtype=torch.int32), lens)
         return t, g, base
 
     def ranges(self, f=0):
@@ -172,7 +177,7 @@ class Renderer:
             pass
 
     # ---- batch construction ------------------------------------------------
-    def make_frames(self, items, outputs=None, need_grad=False) -> list:
+    def make_frames(self, items, outputs=None, need_grad=False, count=False) -> list:
         frames = []
         dev = torch.device("cuda", self.device)
         for k, (scene, view) in enumerate(items):
@@ -184,6 +189,8 @@ class Renderer:
                 T = torch.empty((H, W), dtype=torch.float32, device=dev)
                 last = torch.empty((H, W), dtype=torch.int32, device=dev)
             fr = FrameIO(scene, view, img, T, last)
+            if count:
+                fr.ncontrib = torch.empty((H, W), dtype=torch.int32, device=dev)
             if need_grad:
                 fr.grads = {k2: torch.empty_like(getattr(scene, k2)) for k2 in PARAMS}
             frames.append(fr)
@@ -198,6 +205,7 @@ class Renderer:
             c.view = view_struct(fr.view)
             c.image, c.final_T, c.last = _ptr(fr.image), _ptr(fr.final_T), _ptr(fr.last)
             c.dL_dimage = _ptr(fr.dL_dimage)
+            c.ncontrib = _ptr(fr.ncontrib)
             if fr.grads is not None:
                 c.grad = L.Sd7SceneGrad(*(_ptr(fr.grads[k]) for k in PARAMS))
         return arr
@@ -245,7 +253,7 @@ class Renderer:
             if np.any(c[:, L.SD7_CNT_FLAGS] & L.SD7_FLAG_PAIR_OVERFLOW):
                 need = int(sum((int(x) + 4095) // 4096 * 4096 for x in c[:, L.SD7_CNT_NEEDED]))
                 b2 = self.batch(frames, need)
-                prefix = int(b.layout.off_pair_tile)
+                prefix = int(b.layout.off_pair_g)
                 b2.ws[:prefix].copy_(b.ws[:prefix])
                 b = b2
                 self.stage("sd7_bin", b, stream)
@@ -253,8 +261,8 @@ class Renderer:
         self.stage("sd7_rasterize", b, stream)
         return b
 
-    def render(self, scene: GaussianScene, view, capacity=None, stream=None) -> Batch:
-        return self.render_frames(self.make_frames([(scene, view)]), capacity, stream)
+    def render(self, scene: GaussianScene, view, capacity=None, stream=None, count=False) -> Batch:
+        return self.render_frames(self.make_frames([(scene, view)], count=count), capacity, stream)
 
     def backward(self, b: Batch, dL_dimages, stream=None):
         """Reverse pass of a rendered batch: returns per-frame gradient dicts."""

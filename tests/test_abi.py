@@ -36,7 +36,7 @@ def test_struct_sizes_match_the_header_layout():
     # sd7_view: 16 floats, 2 int32, t, d[3], 2 lambdas, bg[3] -> 108 bytes
     assert ctypes.sizeof(L.Sd7View) == 108
     assert ctypes.sizeof(L.Sd7Scene) == 56
-    assert ctypes.sizeof(L.Sd7Frame) == 56 + 108 + 4 + 4 * 8 + 6 * 8  # view padded to 8
+    assert ctypes.sizeof(L.Sd7Frame) == 56 + 108 + 4 + 4 * 8 + 6 * 8 + 8  # view padded to 8
 
 
 def _frame(n=100, W=64, H=48, ptr=0x1000):
@@ -69,7 +69,7 @@ def test_plan_layout(lib):
     offs = [getattr(lay, k) for k in L._OFFS]
     assert all(o % 256 == 0 for o in offs)
     assert offs == sorted(offs) and lay.bytes >= offs[-1]
-    assert lay.off_pair_g - lay.off_pair_tile >= 4 * 123457
+    assert lay.off_ranges - lay.off_pair_g >= 4 * 123457
     rc, lay1 = _plan(lib, [_frame(10, 16, 16)], 0)
     assert rc == L.SD7_OK and lay1.tile_sort_passes == 1
 

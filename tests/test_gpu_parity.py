@@ -152,7 +152,9 @@ def test_image_parity(R, case, report):
     on every unflagged pixel."""
     scene, views = CASES[case]()
     v = views[0]
-    b = _render(R, scene, v)
+    print(f"[render] n={scene.n} {v.W}x{v.H} with contributor counts", flush=True)
+    b = R.render(_gs(scene), v, count=True)
+    torch.cuda.synchronize()
     ora = oracle.render(scene, v)
     img = b.frames[0].image.cpu().numpy()
     err, nflag = image_check(img, ora)
@@ -162,6 +164,34 @@ def test_image_parity(R, case, report):
     mask = ora.flags == 0
     assert np.abs(T - ora.final_T)[mask].max() <= 1e-4
     assert nflag <= 0.02 * v.W * v.H
+    # the contributor set itself: counts equal wherever no decision is within
+    # FP32 rounding of its threshold (no impact filter here)
+    strict = oracle.render(scene, v, flags={"impact_min": 0.0})
+    m0 = strict.flags == 0
+    nc = b.frames[0].ncontrib.cpu().numpy()
+    assert np.array_equal(nc[m0], strict.ncontrib[m0])
+
+
+def test_radix_binner_for_frames_above_32768_tiles(R, report):
+    """A 2912x2912 frame has 182 x 182 = 33,124 tiles, beyond the counting
+    binner's LDS budget: binning falls back to the radix tile sort, which must
+    give the same bit-exact lists and an oracle-matching image."""
+    scene = scenegen.make_scene(20000, 17, h=1.0, sigma_off=0.1)
+    v = scenegen.make_views(1, 17, r=3.0, W=2912, H=2912)[0]
+    b = _render(R, scene, v)
+    counts = b.counts().cpu().numpy()
+    dk = b.depth_key().cpu().numpy().view(np.uint32)
+    rect = b.rect().cpu().numpy().view(np.uint32)
+    order, tile, g, ranges = cpu_bin(dk, rect, 182, 182 * 182)
+    t_gpu, g_gpu, base = b.pairs(0, counts)
+    assert np.array_equal(t_gpu.cpu().numpy(), tile)
+    assert np.array_equal(g_gpu.cpu().numpy(), g)
+    img = b.frames[0].image.cpu().numpy()
+    crop = (1440, 1440, 32, 32)
+    ora = oracle.render(scene, v, crop=crop)
+    err, nflag = image_check(img[:, 1440:1472, 1440:1472], ora)
+    report("radix_fallback", pairs=int(counts[0, 1]), max_err=err, flagged=nflag)
+    assert err <= 1e-4
 
 
 def test_empty_and_transparent_scenes(R):
