@@ -148,7 +148,8 @@ typedef struct {
     sd7_view view;
     float* image;            /* out [3][H][W]: C + T_final * bg */
     float* final_T;          /* out [H][W]: transmittance after compositing */
-    uint32_t* last;          /* out [H][W]: tile-list entries up to the last contributor */
+    uint32_t* last;          /* out [H][W]: tile-list entries the pixel consumed: those before
+                                the one that stopped it, else the whole list */
     const float* dL_dimage;  /* in  [3][H][W]: backward only (may be NULL otherwise) */
     sd7_scene_grad grad;     /* out: backward only (may be NULL otherwise) */
     uint32_t* ncontrib;      /* optional out [H][W]: splats that contributed to the pixel;

@@ -1,14 +1,15 @@
 // Depth-aware, opacity-blended front-to-back compositing (Sec. 4.4) and its
 // reverse.
 //
-// One wave64 per 16x16 tile; lane l owns a 1x4 column of pixels (x = l % 16,
-// rows 4 (l / 16) .. +3), so the column offset dx and its products are shared
-// by the lane's four pixels.  The wave walks the tile's list in order; a
+// One wave64 per 16x16 tile.  Lane l owns one pixel in each of the tile's
+// four 4-row bands: column l % 16, rows l / 16 + 4k (k = 0..3), so the column
+// offset dx and its products are shared by the lane's four pixels, and band
+// k is pixel k of every lane.  The wave walks the tile's list in order; a
 // splat record is the same for every lane, so it is read with scalar loads
-// through the scalar cache into SGPRs (no LDS staging, no barriers) and the
-// vector ALUs take it as scalar operands.  The wave leaves the list as soon
-// as all 256 pixels are saturated, and skips the blend of any splat that
-// reaches none of them.
+// through the scalar cache into SGPRs (no LDS staging, no barriers), one
+// splat ahead of the one being blended, and the vector ALUs take it as scalar
+// operands.  A band none of whose 64 pixels the splat reaches skips the
+// blend; the wave leaves the list as soon as all 256 pixels have stopped.
 //
 // Per (pixel, splat), with the record's exponent coefficients
 // (A, B, C) = -(a, 2b, c) log2(e) / 2 and lo = log2(alpha_c):
@@ -16,6 +17,8 @@
 //   the splat counts at the pixel iff p >= log2(1/255);
 //   alpha = min(0.99, 2^p); w = T alpha; T' = T - w;
 //   stop before the splat if T' < 1e-4, else C += rgb w, T = T'.
+// The forward and reverse kernels evaluate these with the same explicit
+// fused operations, so they take the same decisions.
 #include "common.h"
 
 namespace sd7 {
@@ -37,6 +40,21 @@ __device__ __forceinline__ Splat load_splat(const float4* __restrict__ rec, uint
 
 __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 
+// log2 of the splat's opacity at the lane's four pixels (sample column fx,
+// sample rows fy[k]); also returns dx, B dx and the row offsets dy.
+__device__ __forceinline__ void splat_exponents(const Splat& s, float fx, const float fy[4], float& dx,
+                                                float& Bdx, float dy[4], float p[4])
+{
+    dx = s.u - fx;
+    const float base = fmaf(s.A * dx, dx, s.lo);
+    Bdx = s.B * dx;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        dy[k] = s.v - fy[k];
+        p[k] = fmaf(dy[k], fmaf(s.C, dy[k], Bdx), base);
+    }
+}
+
 template <bool COUNT>
 __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab, BlockMap bm,
                                                const uint2* __restrict__ ranges,
@@ -49,16 +67,17 @@ __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab,
     const uint32_t tx = tile % F.tiles_x, ty = tile / F.tiles_x;
     const uint32_t lane = threadIdx.x;
     const uint32_t px = tx * kTile + (lane & 15);
-    const uint32_t py0 = ty * kTile + (lane >> 4) * 4;
+    const uint32_t py0 = ty * kTile + (lane >> 4);  // band k: row py0 + 4k
     const float fx = (float)px + 0.5f;
-    // A finished pixel (saturated, or outside the image) moves its sample row
-    // to kFar: its exponent becomes -inf there (C < 0), so it never passes the
-    // opacity test again and needs no flag of its own.
+    // A pixel that has stopped (or lies outside the image) moves its sample
+    // row to kFar: its exponent becomes -inf there (C < 0), so it never
+    // passes the opacity test again and needs no flag of its own.
     float fy[4], T[4], C0[4], C1[4], C2[4];
     uint32_t last[4], ncon[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        fy[k] = (px < F.W && py0 + k < F.H) ? (float)(py0 + k) + 0.5f : kFar;
+        const uint32_t py = py0 + 4 * k;
+        fy[k] = (px < F.W && py < F.H) ? (float)py + 0.5f : kFar;
         T[k] = 1.0f;
         C0[k] = C1[k] = C2[k] = 0.0f;
         last[k] = 0;
@@ -67,54 +86,57 @@ __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab,
     const uint2 rg = ranges[F.t0 + tile];
     const float4* __restrict__ rec = splat + (size_t)F.g0 * 3;
     const uint32_t gmax = __builtin_amdgcn_readfirstlane(F.n - 1);  // pairs exist only if n > 0
-    for (uint32_t e0 = rg.x; e0 < rg.y; e0 += 8) {
-        if (__ballot(fminf(fminf(fy[0], fy[1]), fminf(fy[2], fy[3])) < kFar) == 0) break;
-        const uint32_t cnt = min(8u, rg.y - e0);
-        for (uint32_t j = 0; j < cnt; ++j) {
-            const uint32_t e = e0 + j;
-            const Splat s = load_splat(rec, min(pair_g[e], gmax));
-            const float dx = s.u - fx;
-            const float base = fmaf(s.A * dx, dx, s.lo);
-            const float Bdx = s.B * dx;
-            float p[4];
+    // The record of the next splat and the index of the one after it are
+    // loaded while a splat is blended.  Past the list's end the loads repeat
+    // its last entry (in bounds, unused); indices are clamped where used.
+    Splat s{};
+    uint32_t g1 = 0;  // index of the splat after s
+    if (rg.x < rg.y) {
+        s = load_splat(rec, min(pair_g[rg.x], gmax));
+        g1 = pair_g[min(rg.x + 1, rg.y - 1)];
+    }
+    for (uint32_t e = rg.x; e < rg.y; ++e) {
+        if (((e - rg.x) & 7) == 0 &&
+            __ballot(fminf(fminf(fy[0], fy[1]), fminf(fy[2], fy[3])) < kFar) == 0)
+            break;
+        const Splat sn = load_splat(rec, min(g1, gmax));
+        const uint32_t g2 = pair_g[min(e + 2, rg.y - 1)];
+        asm volatile("" ::: "memory");  // keep the loads ahead of the blend (no wait here)
+        float dx, Bdx, dy[4], p[4];
+        splat_exponents(s, fx, fy, dx, Bdx, dy, p);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float dy = s.v - fy[k];
-                p[k] = fmaf(dy, fmaf(s.C, dy, Bdx), base);
-            }
-            const float pmax = fmaxf(fmaxf(p[0], p[1]), fmaxf(p[2], p[3]));
-            if (__ballot(pmax >= kLog2AlphaMin) == 0) continue;
-            const uint32_t pos = e - rg.x + 1;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const bool pass = p[k] >= kLog2AlphaMin;
-                const float alpha = fminf(kAlphaMax, exp2_fast(p[k]));
-                const float w = T[k] * alpha;
-                const float Tn = T[k] - w;
-                const bool sat = Tn < kTMin;
-                const bool con = pass && !sat;
-                const float wc = con ? w : 0.0f;
-                C0[k] = fmaf(s.r, wc, C0[k]);
-                C1[k] = fmaf(s.g, wc, C1[k]);
-                C2[k] = fmaf(s.b, wc, C2[k]);
-                T[k] = con ? Tn : T[k];
-                last[k] = con ? pos : last[k];
-                if (COUNT) ncon[k] += con ? 1u : 0u;
-                fy[k] = (pass && sat) ? kFar : fy[k];
+        for (int k = 0; k < 4; ++k) {
+            const bool pass = p[k] >= kLog2AlphaMin;
+            if (__ballot(pass) == 0) continue;  // the splat reaches no pixel of band k
+            const float alpha = pass ? fminf(kAlphaMax, exp2_fast(p[k])) : 0.0f;
+            const float w = T[k] * alpha;
+            const float Tn = fmaf(-T[k], alpha, T[k]);
+            const bool stop = Tn < kTMin;  // only a passing pixel can stop: T >= kTMin before
+            const float wc = stop ? 0.0f : w;
+            C0[k] = fmaf(s.r, wc, C0[k]);
+            C1[k] = fmaf(s.g, wc, C1[k]);
+            C2[k] = fmaf(s.b, wc, C2[k]);
+            T[k] = stop ? T[k] : Tn;
+            if (COUNT) ncon[k] += (pass && !stop) ? 1u : 0u;
+            if (__ballot(stop)) {  // once per pixel: it has consumed the entries before e
+                fy[k] = stop ? kFar : fy[k];
+                last[k] = stop ? e - rg.x : last[k];
             }
         }
+        s = sn;
+        g1 = g2;
     }
     const size_t plane = (size_t)F.W * F.H;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const uint32_t py = py0 + k;
+        const uint32_t py = py0 + 4 * k;
         if (px < F.W && py < F.H) {
             const size_t pix = (size_t)py * F.W + px;
             F.image[pix] = C0[k] + T[k] * F.bg[0];
             F.image[plane + pix] = C1[k] + T[k] * F.bg[1];
             F.image[2 * plane + pix] = C2[k] + T[k] * F.bg[2];
             F.final_T[pix] = T[k];
-            F.last[pix] = last[k];
+            F.last[pix] = fy[k] < kFar ? rg.y - rg.x : last[k];  // a pixel that never stopped used all
             if (COUNT && F.ncontrib) F.ncontrib[pix] = ncon[k];
         }
     }
@@ -150,8 +172,8 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v)
     return v;
 }
 
-// Front-to-back recomputation: for each splat up to the pixel's last
-// contributor, with S = C_out - sum_{j<=i} rgb_j w_j (the colour still to come,
+// Front-to-back recomputation: for each of the list entries the pixel
+// consumed in the forward pass, with S = C_out - sum_{j<=i} rgb_j w_j (the colour still to come,
 // background included):  dC/d rgb_i = w_i,  dC/d alpha_i = rgb_i T_i -
 // S_i / (1 - alpha_i).  Per lane the four pixels' terms are folded into sums
 // (S0 = sum s, S1 = sum s dy, S2 = sum s dy^2 with s = dl/d alpha * alpha)
@@ -169,7 +191,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const FrameDev* __restrict__ 
     const uint32_t tx = tile % F.tiles_x, ty = tile / F.tiles_x;
     const uint32_t lane = threadIdx.x;
     const uint32_t px = tx * kTile + (lane & 15);
-    const uint32_t py0 = ty * kTile + (lane >> 4) * 4;
+    const uint32_t py0 = ty * kTile + (lane >> 4);  // band k: row py0 + 4k
     const float fx = (float)px + 0.5f;
     const size_t plane = (size_t)F.W * F.H;
     float fy[4], T[4], Co[4][3], gC[4][3], acc[4][3];
@@ -177,7 +199,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const FrameDev* __restrict__ 
     uint32_t lmax = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const uint32_t py = py0 + k;
+        const uint32_t py = py0 + 4 * k;
         fy[k] = (float)py + 0.5f;
         T[k] = 1.0f;
         last[k] = 0;
@@ -204,17 +226,11 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const FrameDev* __restrict__ 
         const uint32_t g = min(pair_g[e], gmax);
         const Splat s = load_splat(rec, g);
         const uint32_t pos = e - rg.x;
-        const float dx = s.u - fx;
-        const float base = fmaf(s.A * dx, dx, s.lo);
-        const float Bdx = s.B * dx;
-        float p[4], dyv[4];
+        float dx, Bdx, dyv[4], p[4];
+        splat_exponents(s, fx, fy, dx, Bdx, dyv, p);
         bool pass[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            dyv[k] = s.v - fy[k];
-            p[k] = fmaf(dyv[k], fmaf(s.C, dyv[k], Bdx), base);
-            pass[k] = pos < last[k] && p[k] >= kLog2AlphaMin;
-        }
+        for (int k = 0; k < 4; ++k) pass[k] = pos < last[k] && p[k] >= kLog2AlphaMin;
         if (__ballot(pass[0] || pass[1] || pass[2] || pass[3]) == 0) continue;
         float S0 = 0.f, S1 = 0.f, S2 = 0.f, Sr = 0.f, Sg = 0.f, Sb = 0.f;
 #pragma unroll
@@ -222,7 +238,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const FrameDev* __restrict__ 
             const float raw = exp2_fast(p[k]);
             const float alpha = fminf(kAlphaMax, raw);
             const float w = T[k] * alpha;
-            const float Tn = T[k] - w;
+            const float Tn = fmaf(-T[k], alpha, T[k]);
             const bool con = pass[k] && !(Tn < kTMin);
             const float wc = con ? w : 0.0f;
             acc[k][0] = fmaf(s.r, wc, acc[k][0]);
