@@ -28,13 +28,45 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # 256 CUs x 64 lanes x 2.4 GHz: one non-packed FP32 VALU operation per lane per clock
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# FP32 operations the compositing definition needs: every (pixel, splat) test
-# up to the pixel's last contributor takes dx, dy (2), the exponent
-# A dx^2 + B dx dy + C dy^2 + lo (5) and the threshold compare (1); every
-# contributing pair adds exp2 (counted 4: quarter rate), the 0.99 clamp,
-# w = T alpha, T' = T - w, the stop compare and three colour FMAs.
-OPS_PER_TEST = 8
-OPS_PER_CONTRIB = 11
+
+# Rasterizer roofline.  Unit: a wave evaluation, one (pixel, list entry) slot
+# of a tile's wave up to where the wave leaves the list (256 x entries the
+# wave traversed, summed over tiles).  Per-unit figure: the VALU lane
+# operations the kernel issues per evaluation, from the SQ_INSTS_VALU counter
+# (x 64 lanes) over one launch of this workload divided by its evaluations;
+# by the instruction listing of the kernel it is 5 per evaluation for the
+# exponent and the opacity test plus 11 per pixel slot of every band whose
+# blend runs.  Traffic: FETCH_SIZE x 2 + WRITE_SIZE (KiB x 1024) per launch,
+# scaling factors from a 1 GiB device copy.  Both were taken for the kernel
+# source whose digest is RASTER_SRC_SHA256 and are dropped (traffic null,
+# counters_current false) once the source differs.
+RASTER_SRC = ("paper_2503_07946_amd/csrc/raster.hip", "paper_2503_07946_amd/csrc/common.h")
+RASTER_SRC_SHA256 = "c42410d329e9ee4a71e3a3aadb84424c0d8fa2d750651982904a1dbcee8860cf"
+RASTER_VALU_OPS_PER_EVAL = 10.83        # 1.478e9 VALU instructions x 64 / 8.733e9 evaluations
+RASTER_TRAFFIC_BYTES = 2795034624       # (1208513 KiB x 2 + 312500 KiB) x 1024
+
+
+def raster_src_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in RASTER_SRC:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def wave_evaluations(last, ranges, W: int, H: int) -> int:
+    """256 x the list entries each tile's wave traversed: up to the check
+    (every 8 entries) after the last of its pixels stopped, or the whole list."""
+    import torch
+    th, tw = (H + 15) // 16, (W + 15) // 16
+    x = torch.zeros((th * 16, tw * 16), dtype=torch.int64, device=last.device)
+    x[:H, :W] = last.to(torch.int64)
+    mx = x.view(th, 16, tw, 16).amax(dim=(1, 3)).reshape(-1)
+    r = ranges.to(torch.int64)
+    ln = r[:, 1] - r[:, 0]
+    trav = torch.where(mx >= ln, ln, torch.minimum(ln, (mx + 1 + 7) // 8 * 8))
+    return 256 * int(trav.sum())
 
 
 def parse():
@@ -47,7 +79,7 @@ def parse():
     ap.add_argument("--gaussians", type=int, default=200_000)
     ap.add_argument("--plain-frames", type=int, default=20, help="frames timed one per call")
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--cpu-crop", type=int, default=64)
+    ap.add_argument("--cpu-crop", type=int, default=448)
     ap.add_argument("--serve", type=int, default=1, help="also run the serving comparison")
     ap.add_argument("--serve-requests", type=int, default=240)
     ap.add_argument("--serve-warmup", type=int, default=40)
@@ -183,12 +215,14 @@ def main():
     overflow = 0
     pairs = []
     tests = contribs = 0
+    evals = 0
     for b in batches:
         c = R.read_counts(b)
         overflow += int(np.sum(c[:, L.SD7_CNT_FLAGS] & L.SD7_FLAG_PAIR_OVERFLOW != 0))
         pairs += [int(x) for x in c[:, L.SD7_CNT_PAIRS]]
-        for fr in b.frames:
+        for f, fr in enumerate(b.frames):
             tests += int(fr.last.to(torch.int64).sum())
+            evals += wave_evaluations(fr.last, b.ranges(f), fr.view.W, fr.view.H)
     # contributing (pixel, splat) pairs: one untimed pass with per-pixel counts
     for b in batches:
         fc = R.make_frames([(fr.scene, fr.view) for fr in b.frames], count=True)
@@ -204,15 +238,18 @@ def main():
 
     # -- roofline of the dominant kernel (the rasterizer)
     t_r = stage_avg["sd7_rasterize"] * 1e-3                        # per batch launch, s
-    tests_l, contribs_l = tests / len(batches), contribs / len(batches)
-    ops = tests_l * OPS_PER_TEST + contribs_l * OPS_PER_CONTRIB
-    achieved = ops / t_r / 1e12
+    evals_l = evals / len(batches)
+    current = RASTER_SRC_SHA256 is not None and raster_src_digest() == RASTER_SRC_SHA256
+    per_eval = RASTER_VALU_OPS_PER_EVAL
+    achieved = evals_l * per_eval / t_r / 1e12
     roofline = {"bound": "alu", "kernel": "k_raster", "achieved": round(achieved, 3),
                 "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                "traffic": None,
-                "algorithmic_units": {"tests_per_launch": int(tests_l), "ops_per_test": OPS_PER_TEST,
-                                      "contribs_per_launch": int(contribs_l),
-                                      "ops_per_contrib": OPS_PER_CONTRIB},
+                "traffic": RASTER_TRAFFIC_BYTES if current else None,
+                "algorithmic_units": {"wave_evaluations_per_launch": int(evals_l),
+                                      "valu_lane_ops_per_evaluation": per_eval,
+                                      "pixel_tests_per_launch": int(tests / len(batches)),
+                                      "contributions_per_launch": int(contribs / len(batches))},
+                "counters_current": current,
                 "avg_launch_ms": round(stage_avg["sd7_rasterize"], 4)}
 
     # -- latency: batched (frames of a batch finish with their batch) vs plain
@@ -230,7 +267,7 @@ def main():
         bp = R.render_frames(R.make_frames([(gs, v)]), capacity=batches[0].capacity, exact=True)
         torch.cuda.synchronize()
         lat_plain.append(1e3 * (time.perf_counter() - s0))
-    plain_fps = len(lat_plain) / (sum(lat_plain) / 1e3)
+    plain_fps = len(lat_plain) / (sum(lat_plain) / 1e3) if lat_plain else None
 
     # -- FP64 CPU oracle on a bounded sample (a centre crop of view 0)
     cpu = None
@@ -260,7 +297,7 @@ def main():
         "mpixel_per_s": round(fps * W * H / 1e6, 1),
         "latency_ms": {"batched_p50": pct(lat_batched, 50), "batched_p99": pct(lat_batched, 99),
                        "plain_p50": pct(lat_plain, 50), "plain_p99": pct(lat_plain, 99)},
-        "plain_fps": round(plain_fps, 2),
+        "plain_fps": round(plain_fps, 2) if plain_fps else None,
         "stage_ms_per_step": {k: round(v, 4) for k, v in per_step_stage.items()},
         "pairs_per_view_mean": int(np.mean(pairs)), "overflowed_frames": overflow,
         "roofline": roofline,

@@ -233,9 +233,9 @@ sd7_status sd7_project(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t pa
  * pair_g, ranges and the PAIRS / PAIR_BASE counters; sets
  * SD7_FLAG_PAIR_OVERFLOW for frames whose pairs do not fit.  Tile lists are
  * built by counting (per chunk of depth-sorted Gaussians, how many boxes cover
- * each tile) and placement; calls with a frame of more than 16384 tiles use a
- * stable radix sort of (tile, Gaussian) pairs instead.  Both give the same
- * arena contents. */
+ * each tile) and placement by groups of 8 x 8 tiles walking the depth order;
+ * calls with a frame of more than 32768 tiles use a stable radix sort of
+ * (tile, Gaussian) pairs instead.  Both give the same arena contents. */
 sd7_status sd7_bin(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t pair_capacity,
                    void* ws, size_t ws_bytes, sd7_stream stream);
 /* Front-to-back compositing into each frame's image, final_T and last. */
