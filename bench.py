@@ -185,7 +185,7 @@ def main():
         batches.append(R.batch(frames, cap))
     torch.cuda.synchronize()
 
-    stages = ("sd7_slice", "sd7_project", "sd7_bin", "sd7_rasterize")
+    stages = ("sd7_slice_project", "sd7_bin", "sd7_rasterize")
     ev = []
 
     def step(record=False):

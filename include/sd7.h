@@ -229,6 +229,12 @@ sd7_status sd7_slice(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t pair
 /* Sec. 4.4 projection: writes splat, rect, depth_key and the KEPT counters. */
 sd7_status sd7_project(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t pair_capacity,
                        void* ws, size_t ws_bytes, sd7_stream stream);
+/* sd7_slice followed by sd7_project in one pass (Sec. 4.2, Sec. 4.4): frames
+ * of the call that share a scene (the same six parameter arrays and n) are
+ * sliced together, the view-independent part of each Gaussian's slice formed
+ * once.  Outputs are bitwise those of the two separate calls. */
+sd7_status sd7_slice_project(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t pair_capacity,
+                             void* ws, size_t ws_bytes, sd7_stream stream);
 /* Depth sort of the kept Gaussians, then the tile lists: writes order,
  * pair_g, ranges and the PAIRS / PAIR_BASE counters; sets
  * SD7_FLAG_PAIR_OVERFLOW for frames whose pairs do not fit.  Tile lists are

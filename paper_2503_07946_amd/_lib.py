@@ -55,7 +55,7 @@ class Sd7Layout(ctypes.Structure):
                    ("tile0", ctypes.c_int64 * SD7_MAX_FRAMES)])
 
 
-STAGES = ("sd7_slice", "sd7_project", "sd7_bin", "sd7_rasterize", "sd7_render",
+STAGES = ("sd7_slice", "sd7_project", "sd7_slice_project", "sd7_bin", "sd7_rasterize", "sd7_render",
           "sd7_rasterize_backward", "sd7_project_backward", "sd7_slice_backward")
 EXPORTS = ("sd7_create", "sd7_destroy", "sd7_last_error", "sd7_plan", "sd7_read_counts") + STAGES
 

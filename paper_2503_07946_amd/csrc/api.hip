@@ -13,6 +13,7 @@
 #include "common.h"
 #include "slice.hip"
 #include "project.hip"
+#include "slice_project.hip"
 #include "bin.hip"
 #include "raster.hip"
 
@@ -67,6 +68,8 @@ struct Plan {
     uint32_t max_wt_depth, max_wt_pairs;
     size_t hist_entries, partial_entries;
     BlockMap gmap;   // blocks of 256 Gaussians per frame
+    SceneGroups sgrp;  // frames sharing a scene; blocks of 256 Gaussians per group
+    uint32_t sblocks;
     BlockMap tmap;   // one block per tile
     uint32_t gblocks, tblocks;
     // counting binner (frames of at most kMaxCountTiles tiles)
@@ -150,6 +153,37 @@ sd7_status make_plan(const sd7_frame* fr, int nf, int64_t cap, Plan& P, bool nee
         P.matrix_entries += (size_t)P.nch[f] * tx * ty;
     }
     P.gmap.start[nf] = P.gblocks;
+    // scene groups (same parameter arrays and n), in order of first appearance
+    {
+        int owner[SD7_MAX_FRAMES], head[SD7_MAX_FRAMES];
+        int ng = 0;
+        for (int f = 0; f < nf; ++f) {
+            const sd7_scene& A = fr[f].scene;
+            owner[f] = -1;
+            for (int g = 0; g < ng && owner[f] < 0; ++g) {
+                const sd7_scene& B = fr[head[g]].scene;
+                if (A.n == B.n && A.mu_p == B.mu_p && A.mu_t == B.mu_t && A.mu_d == B.mu_d && A.L == B.L &&
+                    A.alpha == B.alpha && A.sh == B.sh)
+                    owner[f] = g;
+            }
+            if (owner[f] < 0) {
+                head[ng] = f;
+                owner[f] = ng++;
+            }
+        }
+        int q = 0;
+        for (int g = 0; g < ng; ++g) {
+            P.sgrp.first[g] = (uint8_t)q;
+            P.sgrp.start[g] = P.sblocks;
+            const int q0 = q;
+            for (int f = 0; f < nf; ++f)
+                if (owner[f] == g) P.sgrp.frame[q++] = (uint8_t)f;
+            P.sblocks += ceil_div(fr[head[g]].scene.n, kBlock) * ceil_div(q - q0, kFramesPerLane);
+        }
+        P.sgrp.first[ng] = (uint8_t)q;
+        P.sgrp.start[ng] = P.sblocks;
+        P.sgrp.ng = ng;
+    }
     P.tmap.start[nf] = P.tblocks;
     P.cmap.start[nf] = P.cblocks;
     P.kmap.start[nf] = P.kblocks;
@@ -365,6 +399,20 @@ sd7_status do_project(const Call& c)
                                                  c.at<float>(L.off_alpha_c), c.at<float4>(L.off_splat),
                                                  c.at<uint2>(L.off_rect), c.at<uint32_t>(L.off_depth_key), c.counts);
     LAUNCH_CHECK("k_project");
+    return SD7_OK;
+}
+
+// Slice + project over scene groups (bitwise the same outputs as do_slice
+// followed by do_project).
+sd7_status do_slice_project(const Call& c)
+{
+    const sd7_layout& L = c.P.L;
+    sd7_status s = fill(c, c.counts, (size_t)SD7_CNT_WORDS * L.nframes, 0);
+    if (s != SD7_OK || c.P.sblocks == 0) return s;
+    k_slice_project<<<c.P.sblocks, kBlock, 0, c.st>>>(
+        c.tab, c.P.sgrp, c.at<float>(L.off_mu_c), c.at<float>(L.off_cov_c), c.at<float>(L.off_alpha_c),
+        c.at<float4>(L.off_splat), c.at<uint2>(L.off_rect), c.at<uint32_t>(L.off_depth_key), c.counts);
+    LAUNCH_CHECK("k_slice_project");
     return SD7_OK;
 }
 
@@ -585,11 +633,11 @@ sd7_status sd7_plan(const sd7_frame* frames, int nf, int64_t pair_capacity, sd7_
 
 STAGE(sd7_slice, false, { return do_slice(c); })
 STAGE(sd7_project, false, { return do_project(c); })
+STAGE(sd7_slice_project, false, { return do_slice_project(c); })
 STAGE(sd7_bin, false, { return do_bin(c); })
 STAGE(sd7_rasterize, false, { return do_raster(c); })
 STAGE(sd7_render, false, {
-    if ((s = do_slice(c)) != SD7_OK) return s;
-    if ((s = do_project(c)) != SD7_OK) return s;
+    if ((s = do_slice_project(c)) != SD7_OK) return s;
     if ((s = do_bin(c)) != SD7_OK) return s;
     return do_raster(c);
 })

@@ -83,6 +83,28 @@ __device__ __forceinline__ int frame_of_block(const BlockMap& bm, uint32_t b)
     return lo;
 }
 
+// Frames of a call grouped by scene (same parameter arrays): group g owns
+// frame[first[g]] .. frame[first[g + 1] - 1] and launch blocks start[g] ..
+// start[g + 1] - 1 (kernel argument): ceil(n / kBlock) runs of Gaussians
+// times ceil(frames / kFramesPerLane) frame chunks.
+constexpr uint32_t kFramesPerLane = 16;
+struct SceneGroups {
+    uint32_t start[SD7_MAX_FRAMES + 1];
+    uint8_t first[SD7_MAX_FRAMES + 1];
+    uint8_t frame[SD7_MAX_FRAMES];
+    int ng;
+};
+
+__device__ __forceinline__ int group_of_block(const SceneGroups& sg, uint32_t b)
+{
+    int lo = 0, hi = sg.ng - 1;
+    while (lo < hi) {  // largest g with start[g] <= b
+        int mid = (lo + hi + 1) >> 1;
+        if (sg.start[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 // A segment of a segmented sort: one frame's elements.
 struct SortSeg {
     uint32_t in_base;    // first element in the input arrays

@@ -119,6 +119,76 @@ __device__ __forceinline__ bool project_one(const FrameDev& F, const float m[3],
     return true;
 }
 
+// SH coefficient j = 3k + ch of Gaussian i, read from the scene.
+struct ShGlobal {
+    const float* __restrict__ sh;
+    uint32_t n;
+    __device__ __forceinline__ float operator()(int j, uint32_t i) const { return sh[(size_t)j * n + i]; }
+};
+
+// Projection, footprint, colour and the splat record of Gaussian i of frame F
+// from its FP32 slice outputs; returns whether the Gaussian is kept.  sh(j, i)
+// gives SH coefficient j of the Gaussian.
+template <class Sh>
+__device__ __forceinline__ bool project_emit(const FrameDev& F, uint32_t i, float ac, const float m[3],
+                                             const float cv[6], const Sh& sh, float4* __restrict__ splat,
+                                             uint2* __restrict__ rect, uint32_t* __restrict__ depth_key)
+{
+    const size_t g0 = F.g0;
+    Proj p;
+    bool keep = ac >= kAlphaMin && project_one(F, m, cv, p);
+    uint32_t rx0 = 0, ry0 = 0, rx1 = 0, ry1 = 0;
+    if (keep) {
+        const float k = 2.0f * logf(ac / kAlphaMin);
+        const float hx = sqrtf(k * p.s00), hy = sqrtf(k * p.s11);
+        float tx0 = floorf((p.u - hx) / (float)kTile), tx1 = floorf((p.u + hx) / (float)kTile);
+        float ty0 = floorf((p.v - hy) / (float)kTile), ty1 = floorf((p.v + hy) / (float)kTile);
+        tx0 = fmaxf(tx0, 0.0f);
+        ty0 = fmaxf(ty0, 0.0f);
+        tx1 = fminf(tx1, (float)F.tiles_x - 1.0f);
+        ty1 = fminf(ty1, (float)F.tiles_y - 1.0f);
+        keep = tx0 <= tx1 && ty0 <= ty1;  // false for NaN too
+        if (keep) {
+            rx0 = (uint32_t)tx0; ry0 = (uint32_t)ty0;
+            rx1 = (uint32_t)tx1 + 1; ry1 = (uint32_t)ty1 + 1;
+        }
+    }
+    float rgb[3] = {0.f, 0.f, 0.f};
+    if (keep) {
+        const float dx = m[0] - F.c[0], dy = m[1] - F.c[1], dz = m[2] - F.c[2];
+        const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+        float Y[16];
+        sh_eval(dx * inv, dy * inv, dz * inv, Y);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float s = 0.5f;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) s += sh(3 * k + ch, i) * Y[k];
+            rgb[ch] = fmaxf(s, 0.0f);
+        }
+    }
+    float4* rec = splat + (g0 + i) * 3;
+    if (keep) {
+        // exponent of alpha in base 2: A dx^2 + B dx dy + C dy^2 + log2(alpha_c)
+        rec[0] = make_float4(p.u, p.v, kNegHalfLog2e * p.a, kNegLog2e * p.b);
+        rec[1] = make_float4(kNegHalfLog2e * p.c, log2f(ac), rgb[0], rgb[1]);
+        rec[2] = make_float4(rgb[2], p.x[2], ac, 0.f);
+    } else {
+        rec[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+        rec[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        rec[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    rect[g0 + i] = make_uint2(rx0 | (ry0 << 16), rx1 | (ry1 << 16));
+    depth_key[g0 + i] = keep ? __float_as_uint(p.x[2]) : kCulled;
+    return keep;
+}
+
+__device__ __forceinline__ void wave_kept(bool keep, uint32_t* __restrict__ counts, int f)
+{
+    const uint64_t kept = __ballot(keep);
+    if (__lane_id() == 0 && kept) atomicAdd(&counts[f * SD7_CNT_WORDS + SD7_CNT_KEPT], (uint32_t)__popcll(kept));
+}
+
 __global__ __launch_bounds__(kBlock) void k_project(const FrameDev* __restrict__ tab, BlockMap bm,
                                                     const float* __restrict__ mu_c, const float* __restrict__ cov_c,
                                                     const float* __restrict__ alpha_c, float4* __restrict__ splat,
@@ -128,65 +198,18 @@ __global__ __launch_bounds__(kBlock) void k_project(const FrameDev* __restrict__
     const int f = frame_of_block(bm, blockIdx.x);
     const FrameDev& F = tab[f];
     const uint32_t i = (blockIdx.x - bm.start[f]) * kBlock + threadIdx.x;
-    const bool valid = i < F.n;
     bool keep = false;
-    if (valid) {
+    if (i < F.n) {
         const uint32_t n = F.n;
         const size_t g0 = F.g0;
-        const float ac = alpha_c[g0 + i];
         float m[3], cv[6];
 #pragma unroll
         for (int a = 0; a < 3; ++a) m[a] = mu_c[3 * g0 + (size_t)a * n + i];
 #pragma unroll
         for (int e = 0; e < 6; ++e) cv[e] = cov_c[6 * g0 + (size_t)e * n + i];
-        Proj p;
-        keep = ac >= kAlphaMin && project_one(F, m, cv, p);
-        uint32_t rx0 = 0, ry0 = 0, rx1 = 0, ry1 = 0;
-        if (keep) {
-            const float k = 2.0f * logf(ac / kAlphaMin);
-            const float hx = sqrtf(k * p.s00), hy = sqrtf(k * p.s11);
-            float tx0 = floorf((p.u - hx) / (float)kTile), tx1 = floorf((p.u + hx) / (float)kTile);
-            float ty0 = floorf((p.v - hy) / (float)kTile), ty1 = floorf((p.v + hy) / (float)kTile);
-            tx0 = fmaxf(tx0, 0.0f);
-            ty0 = fmaxf(ty0, 0.0f);
-            tx1 = fminf(tx1, (float)F.tiles_x - 1.0f);
-            ty1 = fminf(ty1, (float)F.tiles_y - 1.0f);
-            keep = tx0 <= tx1 && ty0 <= ty1;  // false for NaN too
-            if (keep) {
-                rx0 = (uint32_t)tx0; ry0 = (uint32_t)ty0;
-                rx1 = (uint32_t)tx1 + 1; ry1 = (uint32_t)ty1 + 1;
-            }
-        }
-        float rgb[3] = {0.f, 0.f, 0.f};
-        if (keep) {
-            const float dx = m[0] - F.c[0], dy = m[1] - F.c[1], dz = m[2] - F.c[2];
-            const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-            float Y[16];
-            sh_eval(dx * inv, dy * inv, dz * inv, Y);
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                float s = 0.5f;
-#pragma unroll
-                for (int k = 0; k < 16; ++k) s += F.sh[(size_t)(3 * k + ch) * n + i] * Y[k];
-                rgb[ch] = fmaxf(s, 0.0f);
-            }
-        }
-        float4* rec = splat + (g0 + i) * 3;
-        if (keep) {
-            // exponent of alpha in base 2: A dx^2 + B dx dy + C dy^2 + log2(alpha_c)
-            rec[0] = make_float4(p.u, p.v, kNegHalfLog2e * p.a, kNegLog2e * p.b);
-            rec[1] = make_float4(kNegHalfLog2e * p.c, log2f(ac), rgb[0], rgb[1]);
-            rec[2] = make_float4(rgb[2], p.x[2], ac, 0.f);
-        } else {
-            rec[0] = make_float4(0.f, 0.f, 0.f, 0.f);
-            rec[1] = make_float4(0.f, 0.f, 0.f, 0.f);
-            rec[2] = make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-        rect[g0 + i] = make_uint2(rx0 | (ry0 << 16), rx1 | (ry1 << 16));
-        depth_key[g0 + i] = keep ? __float_as_uint(p.x[2]) : kCulled;
+        keep = project_emit(F, i, alpha_c[g0 + i], m, cv, ShGlobal{F.sh, n}, splat, rect, depth_key);
     }
-    const uint64_t kept = __ballot(keep);
-    if (__lane_id() == 0 && kept) atomicAdd(&counts[f * SD7_CNT_WORDS + SD7_CNT_KEPT], (uint32_t)__popcll(kept));
+    wave_kept(keep, counts, f);
 }
 
 // Reverse of k_project.  d_splat planes per frame: (du, dv, da, db, dc, dop,

@@ -25,45 +25,59 @@ __device__ __forceinline__ double sig(const double* L, int a, int b)
     return s;
 }
 
-struct SliceState {
-    double L[28];
+// View-independent part of the slice: Sigma blocks, chol(Sigma_QQ), V, and
+// chol of the marginal direction block.
+struct SliceFixed {
     double SPP[3][3];
     double SPQ[3][4];
     double C[4][4];     // chol(Sigma_QQ), lower
+    double rC[4];       // 1 / C[k][k]
     double V[3][4];     // Sigma_PQ C^{-T}
-    double u[4];        // C^{-1} r
-    double r[4];
     double CD[3][3];    // chol(Sigma_DD), lower
-    double y[3];        // Sigma_DD^{-1} delta
+    double rCD[3];      // 1 / CD[k][k]
     double s_tt;        // Sigma_t
-    double e_t, e_d;    // exponents lambda_t r_t^2 / Sigma_t and lambda_d delta^T Sigma_d^{-1} delta
     bool ok;
 };
 
-__device__ __forceinline__ void slice_state(const FrameDev& F, uint32_t i, SliceState& S, uint32_t& flag)
+// Per-view part: the residual r = (t - mu_t, d - mu_d) and what follows from it.
+struct SliceView {
+    double u[4];        // C^{-1} r
+    double r[4];
+    double y[3];        // Sigma_DD^{-1} delta (reverse pass only)
+    double e_t, e_d;    // exponents lambda_t r_t^2 / Sigma_t and lambda_d delta^T Sigma_d^{-1} delta
+};
+
+struct SliceState : SliceFixed, SliceView {
+    double L[28];
+};
+
+__device__ __forceinline__ void load_L(const float* __restrict__ Lp, uint32_t n, uint32_t i, double L[28])
 {
-    const uint32_t n = F.n;
 #pragma unroll
-    for (int k = 0; k < 28; ++k) S.L[k] = (double)F.L[(size_t)k * n + i];
+    for (int k = 0; k < 28; ++k) L[k] = (double)Lp[(size_t)k * n + i];
+}
+
+__device__ __forceinline__ void slice_fixed(const double L[28], SliceFixed& S, uint32_t& flag)
+{
     bool ok = true;
 #pragma unroll
     for (int k = 0; k < 7; ++k)
-        if (!(S.L[tri(k, k)] > 0.0)) ok = false;
+        if (!(L[tri(k, k)] > 0.0)) ok = false;
     if (!ok) flag |= SD7_FLAG_NONPOS_DIAG;
 
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b <= a; ++b) S.SPP[a][b] = S.SPP[b][a] = sig(S.L, a, b);
+        for (int b = 0; b <= a; ++b) S.SPP[a][b] = S.SPP[b][a] = sig(L, a, b);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) S.SPQ[a][q] = sig(S.L, 3 + q, a);
+        for (int q = 0; q < 4; ++q) S.SPQ[a][q] = sig(L, 3 + q, a);
     double SQQ[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b <= a; ++b) SQQ[a][b] = SQQ[b][a] = sig(S.L, 3 + a, 3 + b);
+        for (int b = 0; b <= a; ++b) SQQ[a][b] = SQQ[b][a] = sig(L, 3 + a, 3 + b);
     S.s_tt = SQQ[0][0];
 
     // Cholesky of Sigma_QQ
@@ -77,8 +91,9 @@ __device__ __forceinline__ void slice_state(const FrameDev& F, uint32_t i, Slice
             if (a == b) {
                 if (!(s > 0.0)) { ok = false; s = 1.0; }
                 S.C[a][a] = sqrt(s);
+                S.rC[a] = 1.0 / S.C[a][a];
             } else {
-                S.C[a][b] = s / S.C[b][b];
+                S.C[a][b] = s * S.rC[b];
             }
         }
 #pragma unroll
@@ -92,18 +107,8 @@ __device__ __forceinline__ void slice_state(const FrameDev& F, uint32_t i, Slice
             double s = S.SPQ[a][k];
 #pragma unroll
             for (int m = 0; m < k; ++m) s = fma(-S.C[k][m], S.V[a][m], s);
-            S.V[a][k] = s / S.C[k][k];
+            S.V[a][k] = s * S.rC[k];
         }
-    S.r[0] = (double)F.t - (double)F.mu_t[i];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) S.r[1 + k] = (double)F.d[k] - (double)F.mu_d[(size_t)k * n + i];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        double s = S.r[k];
-#pragma unroll
-        for (int m = 0; m < k; ++m) s = fma(-S.C[k][m], S.u[m], s);
-        S.u[k] = s / S.C[k][k];
-    }
     // Cholesky of the marginal direction block Sigma_DD = SQQ[1:4, 1:4]
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -115,32 +120,119 @@ __device__ __forceinline__ void slice_state(const FrameDev& F, uint32_t i, Slice
             if (a == b) {
                 if (!(s > 0.0)) { ok = false; s = 1.0; }
                 S.CD[a][a] = sqrt(s);
+                S.rCD[a] = 1.0 / S.CD[a][a];
             } else {
-                S.CD[a][b] = s / S.CD[b][b];
+                S.CD[a][b] = s * S.rCD[b];
             }
         }
 #pragma unroll
         for (int b = a + 1; b < 3; ++b) S.CD[a][b] = 0.0;
     }
+    if (!(S.s_tt > 0.0)) ok = false;
+    S.ok = ok;
+}
+
+// mu_t and mu_d of the Gaussian, t and d of the view; y only if WITH_Y.
+template <bool WITH_Y>
+__device__ __forceinline__ void slice_view(const SliceFixed& S, double t, const float d[3], double mu_t,
+                                           const double mu_d[3], float lambda_t, float lambda_d, SliceView& W)
+{
+    W.r[0] = t - mu_t;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) W.r[1 + k] = (double)d[k] - mu_d[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double s = W.r[k];
+#pragma unroll
+        for (int m = 0; m < k; ++m) s = fma(-S.C[k][m], W.u[m], s);
+        W.u[k] = s * S.rC[k];
+    }
     double z[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        double s = S.r[1 + k];
+        double s = W.r[1 + k];
 #pragma unroll
         for (int m = 0; m < k; ++m) s = fma(-S.CD[k][m], z[m], s);
-        z[k] = s / S.CD[k][k];
+        z[k] = s * S.rCD[k];
     }
-    S.e_d = (double)F.lambda_d * (z[0] * z[0] + z[1] * z[1] + z[2] * z[2]);
+    W.e_d = (double)lambda_d * (z[0] * z[0] + z[1] * z[1] + z[2] * z[2]);
+    if (WITH_Y) {
 #pragma unroll
-    for (int k = 2; k >= 0; --k) {  // y = CD^{-T} z = Sigma_DD^{-1} delta
-        double s = z[k];
+        for (int k = 2; k >= 0; --k) {  // y = CD^{-T} z = Sigma_DD^{-1} delta
+            double s = z[k];
 #pragma unroll
-        for (int m = k + 1; m < 3; ++m) s = fma(-S.CD[m][k], S.y[m], s);
-        S.y[k] = s / S.CD[k][k];
+            for (int m = k + 1; m < 3; ++m) s = fma(-S.CD[m][k], W.y[m], s);
+            W.y[k] = s * S.rCD[k];
+        }
     }
-    S.e_t = (double)F.lambda_t * S.r[0] * S.r[0] / S.s_tt;
-    if (!(S.s_tt > 0.0)) ok = false;
-    S.ok = ok;
+    W.e_t = (double)lambda_t * W.r[0] * W.r[0] / S.s_tt;
+}
+
+template <bool WITH_Y>
+__device__ __forceinline__ void slice_state(const FrameDev& F, uint32_t i, SliceState& S, uint32_t& flag)
+{
+    const uint32_t n = F.n;
+    load_L(F.L, n, i, S.L);
+    slice_fixed(S.L, S, flag);
+    double mu_d[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) mu_d[k] = (double)F.mu_d[(size_t)k * n + i];
+    slice_view<WITH_Y>(S, (double)F.t, F.d, (double)F.mu_t[i], mu_d, F.lambda_t, F.lambda_d, S);
+}
+
+// Sigma_c = Sigma_PP - V V^T (eq. cond_cov), packed (xx, xy, xz, yy, yz, zz),
+// rounded to FP32; returns whether every entry is finite.
+__device__ __forceinline__ bool slice_cov(const SliceFixed& S, float cv[6])
+{
+    const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {0, 1, 2, 1, 2, 2};
+    bool fin = true;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        double s = S.SPP[pa[e]][pb[e]];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s = fma(-S.V[pa[e]][k], S.V[pb[e]][k], s);
+        fin = fin && isfinite(s);
+        cv[e] = (float)s;
+    }
+    return fin;
+}
+
+// The FP32 outputs of one (frame, Gaussian): mu_c (eq. cond_mean), the packed
+// Sigma_c, alpha_c; zeros (and a device flag) when the slice is undefined.
+__device__ __forceinline__ void slice_outputs(const SliceFixed& S, const SliceView& W, const float mu_p[3],
+                                              const float cv32[6], bool cv_fin, float alpha, float mc[3],
+                                              float cv[6], float& ac, uint32_t& flag)
+{
+    double m[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double s = (double)mu_p[a];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s = fma(S.V[a][k], W.u[k], s);
+        m[a] = s;
+    }
+    double a_c = (double)alpha * exp(-0.5 * (W.e_t + W.e_d));
+    const bool fin = isfinite(m[0]) && isfinite(m[1]) && isfinite(m[2]) && isfinite(a_c) && cv_fin;
+    if (S.ok && !fin) flag |= SD7_FLAG_NONFINITE;
+    if (!S.ok && !(flag & SD7_FLAG_NONPOS_DIAG)) flag |= SD7_FLAG_NONFINITE;
+    const bool good = S.ok && fin;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) mc[a] = good ? (float)m[a] : 0.0f;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) cv[e] = good ? cv32[e] : 0.0f;
+    ac = good ? (float)a_c : 0.0f;
+}
+
+// One atomic per wave for a frame's device flags.
+__device__ __forceinline__ void wave_flags(uint32_t flag, uint32_t* __restrict__ counts, int f)
+{
+    const uint64_t any = __ballot(flag != 0);
+    if (any) {
+        uint32_t fl = flag;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) fl |= __shfl_xor(fl, off);
+        if (__lane_id() == 0) atomicOr(&counts[f * SD7_CNT_WORDS + SD7_CNT_FLAGS], fl);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_slice(const FrameDev* __restrict__ tab, BlockMap bm,
@@ -150,56 +242,25 @@ __global__ __launch_bounds__(kBlock) void k_slice(const FrameDev* __restrict__ t
     const int f = frame_of_block(bm, blockIdx.x);
     const FrameDev& F = tab[f];
     const uint32_t i = (blockIdx.x - bm.start[f]) * kBlock + threadIdx.x;
-    const bool valid = i < F.n;
     uint32_t flag = 0;
-    if (valid) {
+    if (i < F.n) {
         const uint32_t n = F.n;
         SliceState S;
-        slice_state(F, i, S, flag);
-        double mc[3], cv[6], ac;
+        slice_state<false>(F, i, S, flag);
+        float mu_p[3], cv32[6];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            double s = (double)F.mu_p[(size_t)a * n + i];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) s = fma(S.V[a][k], S.u[k], s);
-            mc[a] = s;
-        }
-        const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {0, 1, 2, 1, 2, 2};
-#pragma unroll
-        for (int e = 0; e < 6; ++e) {
-            double s = S.SPP[pa[e]][pb[e]];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) s = fma(-S.V[pa[e]][k], S.V[pb[e]][k], s);
-            cv[e] = s;
-        }
-        ac = (double)F.alpha[i] * exp(-0.5 * (S.e_t + S.e_d));
-        bool fin = isfinite(mc[0]) && isfinite(mc[1]) && isfinite(mc[2]) && isfinite(ac);
-#pragma unroll
-        for (int e = 0; e < 6; ++e) fin = fin && isfinite(cv[e]);
-        if (S.ok && !fin) flag |= SD7_FLAG_NONFINITE;
-        if (!S.ok && !(flag & SD7_FLAG_NONPOS_DIAG)) flag |= SD7_FLAG_NONFINITE;
-        if (!S.ok || !fin) {
-            ac = 0.0;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) mc[a] = 0.0;
-#pragma unroll
-            for (int e = 0; e < 6; ++e) cv[e] = 0.0;
-        }
+        for (int a = 0; a < 3; ++a) mu_p[a] = F.mu_p[(size_t)a * n + i];
+        const bool cv_fin = slice_cov(S, cv32);
+        float mc[3], cv[6], ac;
+        slice_outputs(S, S, mu_p, cv32, cv_fin, F.alpha[i], mc, cv, ac, flag);
         const size_t g0 = F.g0;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) mu_c[3 * g0 + (size_t)a * n + i] = (float)mc[a];
+        for (int a = 0; a < 3; ++a) mu_c[3 * g0 + (size_t)a * n + i] = mc[a];
 #pragma unroll
-        for (int e = 0; e < 6; ++e) cov_c[6 * g0 + (size_t)e * n + i] = (float)cv[e];
-        alpha_c[g0 + i] = (float)ac;
+        for (int e = 0; e < 6; ++e) cov_c[6 * g0 + (size_t)e * n + i] = cv[e];
+        alpha_c[g0 + i] = ac;
     }
-    // one atomic per wave for the device flags
-    const uint64_t any = __ballot(flag != 0);
-    if (any) {
-        uint32_t fl = flag;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) fl |= __shfl_xor(fl, off);
-        if (__lane_id() == 0) atomicOr(&counts[f * SD7_CNT_WORDS + SD7_CNT_FLAGS], fl);
-    }
+    wave_flags(flag, counts, f);
 }
 
 // Reverse of k_slice.  Inputs d_mu_c [3], d_cov_c [6] (packed symmetric: the
@@ -232,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_slice_bwd(const FrameDev* __restrict
 
     uint32_t flag = 0;
     SliceState S;
-    slice_state(F, i, S, flag);
+    slice_state<true>(F, i, S, flag);
     double out_mu_p[3] = {0, 0, 0}, out_mu_t = 0, out_mu_d[3] = {0, 0, 0}, out_alpha = 0;
     double dL[28];
 #pragma unroll

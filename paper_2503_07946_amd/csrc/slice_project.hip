@@ -1,0 +1,92 @@
+// Slice and projection fused over the frames of a call that share a scene
+// (Sec. 4.2 then Sec. 4.4).  The conditional covariance, chol(Sigma_QQ),
+// V = Sigma_PQ C^{-T} and chol(Sigma_DD) do not depend on the view (t, d):
+// one lane per Gaussian forms them once, in FP64 registers, and then walks
+// a run of at most kFramesPerLane of the group's frames, doing only the view-dependent
+// part of the slice (the residual r, mu_c = mu_p + V C^{-1} r, the
+// modulations) and the projection of each.  The scene's parameters are read
+// once per kFramesPerLane frames instead of once per frame, and the sliced
+// statistics go to projection in registers.  The block's SH coefficients are
+// staged in LDS once (48 x 256 floats) and read from there by every frame.
+// The blocks of one run of 256
+// Gaussians (one per frame chunk) are adjacent and laid out contiguously per
+// XCD, so their scene reads meet in one L2.  The arithmetic is that of
+// k_slice and k_project, so every output is bitwise the same as the two
+// separate kernels'.
+#include "common.h"
+
+namespace sd7 {
+
+// SH coefficient j of the block's Gaussian t, staged in LDS (plane-major).
+struct ShLds {
+    const float* s;
+    __device__ __forceinline__ float operator()(int j, uint32_t) const { return s[j * kBlock + threadIdx.x]; }
+};
+
+__global__ __launch_bounds__(kBlock, 3) void k_slice_project(const FrameDev* __restrict__ tab, SceneGroups sg,
+                                                          float* __restrict__ mu_c, float* __restrict__ cov_c,
+                                                          float* __restrict__ alpha_c, float4* __restrict__ splat,
+                                                          uint2* __restrict__ rect, uint32_t* __restrict__ depth_key,
+                                                          uint32_t* __restrict__ counts)
+{
+    const uint32_t lb = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int gi = group_of_block(sg, lb);
+    const FrameDev& F0 = tab[sg.frame[sg.first[gi]]];
+    const uint32_t n = F0.n;
+    const uint32_t nq = sg.first[gi + 1] - sg.first[gi];
+    const uint32_t nchunk = (nq + kFramesPerLane - 1) / kFramesPerLane;
+    const uint32_t b = lb - sg.start[gi];
+    const uint32_t chunk = b % nchunk;
+    const uint32_t i = (b / nchunk) * kBlock + threadIdx.x;
+    const bool valid = i < n;
+    SliceFixed S;
+    float mu_p[3] = {0.f, 0.f, 0.f}, mu_d[3] = {0.f, 0.f, 0.f}, cv32[6];
+    float mu_t = 0.f, alpha = 0.f;
+    bool cv_fin = false;
+    uint32_t flag0 = 0;
+    __shared__ float s_sh[48 * kBlock];
+    if (valid) {
+#pragma unroll 8
+        for (int j = 0; j < 48; ++j) s_sh[j * kBlock + threadIdx.x] = F0.sh[(size_t)j * n + i];
+    }
+    // each lane reads back only what it wrote: no barrier needed
+    if (valid) {
+        double L[28];
+        load_L(F0.L, n, i, L);
+        slice_fixed(L, S, flag0);
+        cv_fin = slice_cov(S, cv32);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) mu_p[a] = F0.mu_p[(size_t)a * n + i];
+        mu_t = F0.mu_t[i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) mu_d[k] = F0.mu_d[(size_t)k * n + i];
+        alpha = F0.alpha[i];
+    }
+    // the group's frames split into nchunk runs of nearly equal length
+    const uint32_t q0 = sg.first[gi] + chunk * nq / nchunk;
+    const uint32_t q1 = sg.first[gi] + (chunk + 1) * nq / nchunk;
+    for (uint32_t q = q0; q < q1; ++q) {
+        const int f = sg.frame[q];
+        const FrameDev& F = tab[f];
+        uint32_t flag = flag0;
+        bool keep = false;
+        if (valid) {
+            SliceView W;
+            const double md[3] = {(double)mu_d[0], (double)mu_d[1], (double)mu_d[2]};
+            slice_view<false>(S, (double)F.t, F.d, (double)mu_t, md, F.lambda_t, F.lambda_d, W);
+            float mc[3], cv[6], ac;
+            slice_outputs(S, W, mu_p, cv32, cv_fin, alpha, mc, cv, ac, flag);
+            const size_t g0 = F.g0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) mu_c[3 * g0 + (size_t)a * n + i] = mc[a];
+#pragma unroll
+            for (int e = 0; e < 6; ++e) cov_c[6 * g0 + (size_t)e * n + i] = cv[e];
+            alpha_c[g0 + i] = ac;
+            keep = project_emit(F, i, ac, mc, cv, ShLds{s_sh}, splat, rect, depth_key);
+        }
+        wave_flags(flag, counts, f);
+        wave_kept(keep, counts, f);
+    }
+}
+
+}  // namespace sd7

@@ -246,7 +246,7 @@ class Renderer:
         larger arena if a frame overflowed."""
         cap = self.default_capacity if capacity is None else int(capacity)
         b = self.batch(frames, cap)
-        for s in ("sd7_slice", "sd7_project", "sd7_bin"):
+        for s in ("sd7_slice_project", "sd7_bin"):
             self.stage(s, b, stream)
         if exact:
             c = self.read_counts(b, stream)

@@ -26,7 +26,7 @@ import numpy as np
 PAIR_ROUND = 4096
 
 
-@dataclass
+@dataclass(eq=False)       # a request is itself: compared by identity
 class Request:
     rid: int
     arrival: float          # seconds since the stream started
@@ -46,7 +46,7 @@ class Request:
         return None if self.done is None else self.done - self.arrival
 
 
-@dataclass
+@dataclass(eq=False)
 class Outcome:
     req: Request
     ok: bool                 # False: pair overflow, needs a retry
@@ -125,7 +125,7 @@ class Scheduler:
                 h, reqs, nbytes = item
                 if not self.ex.ready(h):
                     continue
-                inflight.remove(item)
+                inflight = [x for x in inflight if x is not item]
                 used -= nbytes
                 progressed = True
                 tdone = now()

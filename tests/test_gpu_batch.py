@@ -56,3 +56,32 @@ def test_batch_overflow_defers_only_frames_that_do_not_fit(R):
     assert not c[0, L.SD7_CNT_FLAGS] & L.SD7_FLAG_PAIR_OVERFLOW
     assert c[1, L.SD7_CNT_FLAGS] & L.SD7_FLAG_PAIR_OVERFLOW
     assert np.array_equal(b.frames[0].image.cpu().numpy(), alone.frames[0].image.cpu().numpy())
+
+
+def test_fused_slice_project_equals_separate_calls(R):
+    """sd7_slice_project over scene groups writes bitwise what sd7_slice then
+    sd7_project write: frames of two scenes interleaved (groups of 3 and 2),
+    a scene with no Gaussians, and a scene with a non-positive L diagonal."""
+    from paper_2503_07946_amd.render import GaussianScene
+    sA = scenegen.make_scene(3000, 41, sigma_off=0.15)
+    sB = scenegen.make_scene(1500, 42)
+    sB.L[0, :40] = -sB.L[0, :40]                  # L_00 <= 0: flagged and culled
+    vA = scenegen.make_views(3, 41, r=3.0, W=96, H=64)
+    vB = scenegen.make_views(2, 42, r=2.5, W=40, H=72, lam=0.5)
+    gA, gB = GaussianScene.from_host(sA), GaussianScene.from_host(sB)
+    empty = GaussianScene(*(torch.zeros((k, 0), device="cuda").reshape(-1) if k == 1 else
+                            torch.zeros((k, 0), device="cuda") for k in (3, 1, 3, 28, 1, 48)))
+    items = [(gA, vA[0]), (gB, vB[0]), (empty, vA[1]), (gA, vA[1]), (gB, vB[1]), (gA, vA[2])]
+    print("[batch] fused vs separate slice/project, 6 frames", flush=True)
+    sep = R.batch(R.make_frames(items), 1 << 16)
+    fus = R.batch(R.make_frames(items), 1 << 16)
+    R.stage("sd7_slice", sep)
+    R.stage("sd7_project", sep)
+    R.stage("sd7_slice_project", fus)
+    torch.cuda.synchronize()
+    assert np.array_equal(R.read_counts(sep), R.read_counts(fus))
+    for f in range(len(items)):
+        for name in ("mu_c", "cov_c", "alpha_c", "splat", "rect", "depth_key"):
+            a = getattr(sep, name)(f).cpu().numpy().view(np.uint32)
+            b = getattr(fus, name)(f).cpu().numpy().view(np.uint32)
+            assert np.array_equal(a, b), (f, name)

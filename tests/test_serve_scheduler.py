@@ -3,6 +3,7 @@ a modelled time: admission by memory budget, continuous batching, overflow
 retries, rejection, cancellation, in-flight limits."""
 import threading
 import time
+from dataclasses import dataclass
 
 import pytest
 
@@ -112,6 +113,53 @@ def test_overflow_is_retried_at_the_head_with_the_reported_size():
     assert set(retried) == {3, 7}
     assert all(r.pairs_hint == 12345 for r in retried.values())
     assert st.retries == 2
+
+
+class ArrayView(V):
+    """A view whose == is ambiguous, as with numpy-array fields."""
+
+    def __eq__(self, other):
+        raise ValueError("ambiguous comparison")
+
+    __hash__ = object.__hash__
+
+
+@dataclass
+class Handle:
+    """A launch handle compared by value, its first field a view."""
+    view: object
+    due: float
+    reqs: list
+    nbytes: int
+
+
+class HandleExecutor(FakeExecutor):
+    def launch(self, reqs):
+        (due, rs, nbytes), nb = super().launch(reqs)
+        return Handle(rs[0].view, due, rs, nbytes), nb
+
+    def ready(self, h):
+        return time.perf_counter() >= h.due
+
+    def wait(self, handles, timeout):
+        t = min(h.due for h in handles) - time.perf_counter()
+        if timeout is not None:
+            t = min(t, timeout)
+        if t > 0:
+            time.sleep(t)
+
+    def collect(self, h):
+        return super().collect((h.due, h.reqs, h.nbytes))
+
+
+def test_batches_completing_out_of_order_with_uncomparable_handles():
+    """A later, smaller batch finishes before an earlier large one; taking it
+    off the in-flight list must not compare handles or requests by value."""
+    ex = HandleExecutor(overhead=0.001, per_px=2e-8)
+    reqs = [Request(0, 0.0, 0, ArrayView(512, 512)), Request(1, 0.0005, 0, ArrayView(8, 8))]
+    st = Scheduler(ex, 1 << 30, max_slots=1, max_inflight=2).run(reqs)
+    assert sorted(r.rid for r in st.completed) == [0, 1]
+    assert st.completed[0].rid == 1           # the small one finished first
 
 
 def test_request_larger_than_budget_is_rejected():
