@@ -70,10 +70,16 @@ _lib = None
 
 
 def load(path: str = LIB_PATH):
-    """Load the library (once).  Raises if it is missing."""
+    """Load the library (once).  Raises if it is missing.
+
+    The library and PyTorch must share one HIP runtime: both name it by the
+    same soname, so whichever is loaded first serves the process.  PyTorch
+    is imported first so that its runtime (the one that owns the device
+    memory and streams handed to the library) is that one."""
     global _lib
     if _lib is not None:
         return _lib
+    import torch  # noqa: F401  (loads the process's HIP runtime)
     if not os.path.exists(path):
         raise RuntimeError(f"lib7dgs.so not built at {path}; run __graft_entry__.build() "
                            "(the render path has no CPU fallback)")

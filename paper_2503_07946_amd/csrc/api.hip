@@ -86,7 +86,7 @@ struct Plan {
     size_t ttot;     // workspace offset of the per-tile totals (then their scan)
 };
 
-constexpr uint64_t kBinWaves = 32768;  // (chunk, group) waves the counting binner aims for per call
+constexpr uint64_t kBinWaves = 131072; // (chunk, group) waves the counting binner aims for per call
 constexpr uint64_t kMaxChunks = 128;   // chunks per frame (the depth of the per-tile column scan)
 constexpr size_t kMaxMatrix = (size_t)1 << 28;  // count-matrix entries of one call
 
