@@ -81,6 +81,8 @@ def parse():
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-crop", type=int, default=448)
     ap.add_argument("--serve", type=int, default=1, help="also run the serving comparison")
+    ap.add_argument("--agr", type=int, default=1,
+                    help="also time the full variant with adaptive Gaussian refinement (seeded weights)")
     ap.add_argument("--serve-requests", type=int, default=240)
     ap.add_argument("--serve-warmup", type=int, default=40)
     ap.add_argument("--serve-qps", type=float, default=0.0, help="0: 0.9x the plain path's capacity")
@@ -142,6 +144,50 @@ def serve_bench(a, R, L):
     return {"qps": round(qps, 2), "requests": a.serve_requests, "scenes": sizes,
             "resolutions": [list(r) for r in scenegen.SERVE_RES], "hbm_budget_gb": a.serve_budget_gb,
             "plain": sp, "batched": sb}
+
+
+def agr_bench(a, R, L, scene, views):
+    """The full 7DGS variant: the same scenes and views with adaptive Gaussian
+    refinement (Sec. 4.3) before the slice, weights from scenegen.agr_weights(1)."""
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_2503_07946_amd.render import GaussianScene
+
+    gs = GaussianScene.from_host(scene, agr=scenegen.agr_weights(1))
+    groups = [views[i:i + a.batch] for i in range(0, len(views), a.batch)]
+    batches = []
+    for gv in groups:
+        frames = R.make_frames([(gs, v) for v in gv])
+        c = R.read_counts(R.render_frames(frames, exact=True))
+        need = int(sum((int(p) + 4095) // 4096 * 4096 for p in c[:, L.SD7_CNT_NEEDED]))
+        batches.append(R.batch(frames, int(need * 1.05) + 4096))
+    stream = torch.cuda.current_stream()
+    stages = ("sd7_slice_project", "sd7_bin", "sd7_rasterize")
+    for _ in range(a.warmup):
+        for b in batches:
+            R.stage("sd7_render", b)
+    torch.cuda.synchronize()
+    ev = []
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        for b in batches:
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
+            e[0].record(stream)
+            for k, st in enumerate(stages):
+                R.stage(st, b)
+                e[k + 1].record(stream)
+            ev.append(e)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    over = sum(int(np.sum(R.read_counts(b)[:, L.SD7_CNT_FLAGS] & L.SD7_FLAG_PAIR_OVERFLOW != 0)) for b in batches)
+    per = {st: float(np.mean([e[k].elapsed_time(e[k + 1]) for e in ev])) * len(batches)
+           for k, st in enumerate(stages)}
+    return {"value": round(len(views) * a.steps / dt, 2), "unit": "FPS",
+            "ms_per_step": round(1e3 * dt / a.steps, 3),
+            "stage_ms_per_step": {k: round(v, 4) for k, v in per.items()},
+            "overflowed_frames": over, "weights": "scenegen.agr_weights(1)"}
 
 
 def pct(xs, q):
@@ -285,6 +331,7 @@ def main():
                          f"brute-force compositing), {tc:.2f} s; FPS extrapolated to the full 800x800 frame"}
 
     serving = serve_bench(a, R, L) if a.serve else None
+    agr = agr_bench(a, R, L, scene, views) if a.agr else None
 
     out = {
         "metric": "rendered FPS and Mpixel/s at 1 GPU; p50/p99 frame latency, batched vs plain",
@@ -303,6 +350,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "serving": serving,
+        "agr": agr,
     }
     print(json.dumps(out))
     return 0

@@ -98,14 +98,24 @@ typedef struct sd7_ctx sd7_ctx;
 typedef void* sd7_stream; /* a hipStream_t */
 
 /* A scene of n 7D Gaussians (Sec. 4.1), device memory, FP32 structure of
- * arrays, read only:
+ * arrays, read only (agr optional):
  *   mu_p [3][n]  spatial mean          mu_t [n]      temporal mean
  *   mu_d [3][n]  directional mean      alpha [n]     opacity in (0, 1)
  *   L   [28][n]  Cholesky factor of the 7x7 covariance Sigma = L L^T, lower
  *                triangle packed row-major: entry (i, j), i >= j, in plane
  *                i*(i+1)/2 + j; dimension order (x, y, z, t, dx, dy, dz).
  *                Diagonal entries must be positive (the caller's activation).
- *   sh  [48][n]  SH coefficients, plane 3*k + channel, k = l*l + l + m. */
+ *   sh  [48][n]  SH coefficients, plane 3*k + channel, k = l*l + l + m.
+ *   agr [SD7_AGR_WEIGHTS]  adaptive Gaussian refinement (Sec. 4.3), or NULL
+ *                for the variant without it.  Four two-layer MLPs, in the
+ *                order mu_p, mu_t, mu_d, L, each stored as W1[64][27]
+ *                (row-major), b1[64], W2[C_out][64], b2[C_out] with C_out =
+ *                3, 1, 3, 28.  The input is f = mu_p, mu_t, mu_d, gamma(t)
+ *                with gamma(t) = sin(2^k pi t), cos(2^k pi t), k = 0..9,
+ *                interleaved; the hidden activation is ReLU; each output is
+ *                added to its parameter (the L output in the packing above)
+ *                before the slice.  The reverse calls do not support it. */
+#define SD7_AGR_WEIGHTS 9443
 typedef struct {
     const float* mu_p;
     const float* mu_t;
@@ -114,6 +124,7 @@ typedef struct {
     const float* alpha;
     const float* sh;
     int64_t n;
+    const float* agr;
 } sd7_scene;
 
 /* A pinhole view at time t (host memory, by value).  R_wc is the row-major

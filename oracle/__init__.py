@@ -87,6 +87,8 @@ def lib():
                                  ctypes.POINTER(OraFlagCfg), P, P, P, P, P]
         L.ora_render.restype = ctypes.c_int
         L.ora_sh_basis.argtypes = [ctypes.c_double] * 3 + [P]
+        L.ora_agr_encoding.argtypes = [ctypes.c_double, P]
+        L.ora_agr.argtypes = [i64, P, P, P, P, ctypes.c_double, P, P, P, P, P]
         L.ora_num_threads.restype = ctypes.c_int
         L.ora_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -142,7 +144,50 @@ class Sliced:
     status: np.ndarray
 
 
-def slice_(scene, view) -> Sliced:
+# ---- adaptive Gaussian refinement (Sec. 4.3) --------------------------------
+AGR_K = 10
+AGR_IN = 27
+AGR_HIDDEN = 64
+AGR_OUT = (3, 1, 3, 28)          # MLPs for mu_p, mu_t, mu_d, the packed L
+AGR_WEIGHTS = sum(AGR_HIDDEN * AGR_IN + AGR_HIDDEN + c * AGR_HIDDEN + c for c in AGR_OUT)
+
+
+def agr_encoding(t: float) -> np.ndarray:
+    """gamma(t): sin(2^k pi t), cos(2^k pi t) for k = 0 .. 9, interleaved."""
+    g = np.zeros(2 * AGR_K)
+    lib().ora_agr_encoding(float(t), _p(g))
+    return g
+
+
+@dataclass
+class Refined:
+    """A scene with AGR-refined means and factor (FP64), other fields as given."""
+    n: int
+    mu_p: np.ndarray
+    mu_t: np.ndarray
+    mu_d: np.ndarray
+    L: np.ndarray
+    alpha: np.ndarray
+    sh: np.ndarray
+
+
+def agr(scene, t: float, weights) -> Refined:
+    """mu_p + phi_p(f), mu_t + phi_t(f), mu_d + phi_d(f), l + phi_l(f) with
+    f = mu_p (+) mu_t (+) mu_d (+) gamma(t) (Sec. 4.3; Algorithm 1 steps 1-2).
+    weights: AGR_WEIGHTS values, MLPs p, t, d, l, each W1[64][27], b1[64],
+    W2[C_out][64], b2[C_out]."""
+    n = scene.n
+    w = _f64(np.asarray(weights).reshape(-1))
+    assert w.size == AGR_WEIGHTS
+    arrs = [_f64(scene.mu_p), _f64(scene.mu_t), _f64(scene.mu_d), _f64(scene.L)]
+    out = [np.zeros((3, n)), np.zeros(n), np.zeros((3, n)), np.zeros((28, n))]
+    lib().ora_agr(n, *[_p(a) for a in arrs], float(t), _p(w), *[_p(o) for o in out])
+    return Refined(n, out[0], out[1], out[2], out[3], scene.alpha, scene.sh)
+
+
+def slice_(scene, view, agr_weights=None) -> Sliced:
+    if agr_weights is not None:
+        scene = agr(scene, view.t, agr_weights)
     n = scene.n
     mu_c = np.zeros((3, n)); cov_c = np.zeros((6, n)); ac = np.zeros(n)
     ft = np.zeros(n); fd = np.zeros(n); st = np.zeros(n, np.int32)
@@ -206,8 +251,11 @@ def composite(sliced: Sliced, proj: Projected, view, crop=None, flags=None) -> I
     return Image(img, T, nc, ch, fl)
 
 
-def render(scene, view, crop=None, flags=None) -> Image:
-    """Full FP64 forward of one view (optionally a pixel crop x0, y0, w, h)."""
+def render(scene, view, crop=None, flags=None, agr_weights=None) -> Image:
+    """Full FP64 forward of one view (optionally a pixel crop x0, y0, w, h),
+    with the scene first refined by AGR when weights are given."""
+    if agr_weights is not None:
+        scene = agr(scene, view.t, agr_weights)
     x0, y0, w, h = crop if crop is not None else (0, 0, view.W, view.H)
     n = scene.n
     img = np.zeros((3, h, w)); T = np.zeros((h, w)); nc = np.zeros((h, w), np.int32)

@@ -10,8 +10,12 @@
  *            covariance Sigma = L L^T of Sec. 4.1), the temporal and
  *            directional modulation eq. temp_mod / eq. dir_mod and the
  *            conditional opacity alpha_cond = alpha f_temp f_dir; Algorithm 1
- *            steps 3-6 (AGR, steps 1-2, is the identity: the "w/o AGR" variant
- *            of Table 1).
+ *            steps 3-6.
+ *   agr      Sec. 4.3 (Algorithm 1 steps 1-2), optional: the feature vector
+ *            f = mu_p (+) mu_t (+) mu_d (+) gamma(t) and four two-layer MLPs
+ *            whose outputs are added to mu_p, mu_t, mu_d and the packed L
+ *            before slicing.  Without it the path is the "w/o AGR" variant
+ *            of Table 1.
  *   project  Sec. 4.4: standard perspective (EWA) projection of the
  *            conditional 3D Gaussian to a 2D Gaussian; colour from degree-3
  *            spherical harmonics (Sec. 3, eq. 2, reused unchanged per Sec. 4.1).
@@ -47,6 +51,7 @@
 #define DILATION ((double)0.3f)
 #define JCLAMP ((double)1.3f)
 #define TILE 16
+#define ORA_PI 3.14159265358979323846
 
 static int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
@@ -426,6 +431,57 @@ int ora_composite(int64_t n, const double* mean2d, const double* conic, const do
         }
     }
     return 0;
+}
+
+/* ---- adaptive Gaussian refinement (Sec. 4.3) ------------------------------
+ * gamma(t): for k = 0 .. K-1 the pair sin(2^k pi t), cos(2^k pi t), in that
+ * order.  Each MLP maps f (27) to 64 hidden units, applies the activation
+ * (ReLU: the paper does not name it) and maps to its output; the output is a
+ * residual added to the parameter it refines. */
+void ora_agr_encoding(double t, double* g)
+{
+    for (int k = 0; k < AGR_K; ++k) {
+        const double w = ldexp(ORA_PI, k) * t;
+        g[2 * k] = sin(w);
+        g[2 * k + 1] = cos(w);
+    }
+}
+
+void ora_agr(int64_t n, const double* mu_p, const double* mu_t, const double* mu_d, const double* L,
+             double t, const double* wts, double* r_mu_p, double* r_mu_t, double* r_mu_d, double* r_L)
+{
+    static const int cout[4] = {3, 1, 3, 28};
+    double gam[2 * AGR_K];
+    ora_agr_encoding(t, gam);
+#pragma omp parallel for schedule(static)
+    for (int64_t g = 0; g < n; ++g) {
+        double f[AGR_IN];
+        for (int a = 0; a < 3; ++a) f[a] = mu_p[a * n + g];
+        f[3] = mu_t[g];
+        for (int a = 0; a < 3; ++a) f[4 + a] = mu_d[a * n + g];
+        for (int k = 0; k < 2 * AGR_K; ++k) f[7 + k] = gam[k];
+        double* out[4] = {r_mu_p, r_mu_t, r_mu_d, r_L};
+        const double* base[4] = {mu_p, mu_t, mu_d, L};
+        const double* w = wts;
+        for (int m = 0; m < 4; ++m) {
+            const double* W1 = w;
+            const double* b1 = W1 + AGR_HIDDEN * AGR_IN;
+            const double* W2 = b1 + AGR_HIDDEN;
+            const double* b2 = W2 + cout[m] * AGR_HIDDEN;
+            double h[AGR_HIDDEN];
+            for (int j = 0; j < AGR_HIDDEN; ++j) {
+                double s = b1[j];
+                for (int c = 0; c < AGR_IN; ++c) s += W1[j * AGR_IN + c] * f[c];
+                h[j] = s > 0.0 ? s : 0.0;
+            }
+            for (int o = 0; o < cout[m]; ++o) {
+                double s = b2[o];
+                for (int j = 0; j < AGR_HIDDEN; ++j) s += W2[o * AGR_HIDDEN + j] * h[j];
+                out[m][o * n + g] = base[m][o * n + g] + s;
+            }
+            w = b2 + cout[m];
+        }
+    }
 }
 
 int ora_render(int64_t n, const double* mu_p, const double* mu_t, const double* mu_d,

@@ -76,6 +76,18 @@ int ora_render(int64_t n, const double* mu_p, const double* mu_t, const double* 
                double* image, double* final_T, int32_t* ncontrib, uint64_t* chash,
                uint32_t* flags);
 
+/* Adaptive Gaussian refinement (Sec. 4.3).  wts: the four MLPs in the order
+ * p, t, d, l, each as W1[64][27] (row-major), b1[64], W2[C_out][64], b2[C_out]
+ * with C_out = 3, 1, 3, 28 (AGR_WEIGHTS values in all).  Writes the refined
+ * mu_p[3][n], mu_t[n], mu_d[3][n], L[28][n]. */
+#define AGR_K 10
+#define AGR_IN 27
+#define AGR_HIDDEN 64
+#define AGR_WEIGHTS 9443
+void ora_agr_encoding(double t, double* gamma20);
+void ora_agr(int64_t n, const double* mu_p, const double* mu_t, const double* mu_d, const double* L,
+             double t, const double* wts, double* r_mu_p, double* r_mu_t, double* r_mu_d, double* r_L);
+
 void ora_sh_basis(double x, double y, double z, double* Y);
 int ora_num_threads(void);
 void ora_set_num_threads(int nt);

@@ -16,6 +16,7 @@ SD7_FLAG_NONPOS_DIAG, SD7_FLAG_NONFINITE, SD7_FLAG_PAIR_OVERFLOW = 1, 2, 4
 SD7_CNT_KEPT, SD7_CNT_PAIRS, SD7_CNT_PAIR_BASE, SD7_CNT_FLAGS = 0, 1, 2, 3
 SD7_CNT_NEEDED = 4          # pairs the frame needed (internal word, also set on overflow)
 SD7_CNT_WORDS = 16
+SD7_AGR_WEIGHTS = 9443      # floats of one scene's AGR weights (sd7.h)
 
 P = ctypes.c_void_p
 f32 = ctypes.c_float
@@ -23,7 +24,7 @@ f32 = ctypes.c_float
 
 class Sd7Scene(ctypes.Structure):
     _fields_ = [("mu_p", P), ("mu_t", P), ("mu_d", P), ("L", P), ("alpha", P), ("sh", P),
-                ("n", ctypes.c_int64)]
+                ("n", ctypes.c_int64), ("agr", P)]
 
 
 class Sd7View(ctypes.Structure):

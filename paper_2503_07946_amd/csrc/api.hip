@@ -12,6 +12,7 @@
 
 #include "common.h"
 #include "slice.hip"
+#include "agr.hip"
 #include "project.hip"
 #include "slice_project.hip"
 #include "bin.hip"
@@ -282,6 +283,7 @@ sd7_status upload_table(sd7_ctx* ctx, const sd7_frame* fr, int nf, const Plan& P
         D.g_mu_p = F.grad.mu_p; D.g_mu_t = F.grad.mu_t; D.g_mu_d = F.grad.mu_d;
         D.g_L = F.grad.L; D.g_alpha = F.grad.alpha; D.g_sh = F.grad.sh;
         D.ncontrib = F.ncontrib;
+        D.agr = F.scene.agr;
         D.n = (uint32_t)F.scene.n;
         D.g0 = (uint32_t)P.L.g0[f];
         D.W = (uint32_t)F.view.W;
@@ -312,6 +314,7 @@ struct Call {
     const FrameDev* tab;
     uint32_t* counts;
     bool count;  // some frame asks for per-pixel contributor counts
+    bool agr;    // some frame's scene has AGR weights
     template <class T>
     T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
@@ -333,7 +336,12 @@ sd7_status begin(sd7_ctx* ctx, const sd7_frame* fr, int nf, int64_t cap, void* w
     c.tab = c.at<FrameDev>(c.P.L.off_table);
     c.counts = c.at<uint32_t>(c.P.L.off_counts);
     c.count = false;
-    for (int f = 0; f < nf; ++f) c.count = c.count || fr[f].ncontrib != nullptr;
+    c.agr = false;
+    for (int f = 0; f < nf; ++f) {
+        c.count = c.count || fr[f].ncontrib != nullptr;
+        c.agr = c.agr || fr[f].scene.agr != nullptr;
+    }
+    if (need_bwd && c.agr) return fail(SD7_EINVAL, "the reverse calls do not support AGR scenes");
     return upload_table(ctx, fr, nf, c.P, c.ws, c.st);
 }
 
@@ -388,6 +396,12 @@ sd7_status do_slice(const Call& c)
     k_slice<<<c.P.gblocks, kBlock, 0, c.st>>>(c.tab, c.P.gmap, c.at<float>(L.off_mu_c), c.at<float>(L.off_cov_c),
                                                c.at<float>(L.off_alpha_c), c.counts);
     LAUNCH_CHECK("k_slice");
+    if (c.agr) {  // frames whose scene is refined first (k_slice skipped them)
+        k_agr_slice<<<c.P.gblocks, kBlock, 0, c.st>>>(c.tab, c.P.gmap, c.at<float>(L.off_mu_c),
+                                                       c.at<float>(L.off_cov_c), c.at<float>(L.off_alpha_c),
+                                                       c.counts);
+        LAUNCH_CHECK("k_agr_slice");
+    }
     return SD7_OK;
 }
 
@@ -407,6 +421,10 @@ sd7_status do_project(const Call& c)
 sd7_status do_slice_project(const Call& c)
 {
     const sd7_layout& L = c.P.L;
+    if (c.agr) {  // refined parameters depend on t: nothing to share across frames
+        sd7_status s = do_slice(c);
+        return s != SD7_OK ? s : do_project(c);
+    }
     sd7_status s = fill(c, c.counts, (size_t)SD7_CNT_WORDS * L.nframes, 0);
     if (s != SD7_OK || c.P.sblocks == 0) return s;
     k_slice_project<<<c.P.sblocks, kBlock, 0, c.st>>>(

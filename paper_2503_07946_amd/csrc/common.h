@@ -46,6 +46,7 @@ struct FrameDev {
     float* g_alpha;
     float* g_sh;
     uint32_t* ncontrib;  // optional per-pixel contributor count
+    const float* agr;    // optional AGR weights (SD7_AGR_WEIGHTS floats)
     uint32_t n;        // Gaussians
     uint32_t g0;       // first Gaussian in the concatenated per-Gaussian arrays
     uint32_t W, H;

@@ -241,6 +241,7 @@ __global__ __launch_bounds__(kBlock) void k_slice(const FrameDev* __restrict__ t
 {
     const int f = frame_of_block(bm, blockIdx.x);
     const FrameDev& F = tab[f];
+    if (F.agr) return;  // uniform: refined and sliced by k_agr_slice
     const uint32_t i = (blockIdx.x - bm.start[f]) * kBlock + threadIdx.x;
     uint32_t flag = 0;
     if (i < F.n) {

@@ -21,8 +21,12 @@ def _ptr(t):
 class GaussianScene:
     """A scene of 7D Gaussians resident in device memory (FP32 planes)."""
 
-    def __init__(self, mu_p, mu_t, mu_d, L_, alpha, sh):
+    def __init__(self, mu_p, mu_t, mu_d, L_, alpha, sh, agr=None):
         self.mu_p, self.mu_t, self.mu_d, self.L, self.alpha, self.sh = mu_p, mu_t, mu_d, L_, alpha, sh
+        self.agr = agr  # optional AGR weights (Sec. 4.3), SD7_AGR_WEIGHTS floats
+        if agr is not None and (agr.dtype != torch.float32 or not agr.is_contiguous()
+                                or agr.device.type != "cuda" or agr.numel() != L.SD7_AGR_WEIGHTS):
+            raise ValueError(f"agr: need a contiguous float32 device tensor of {L.SD7_AGR_WEIGHTS} values")
         n = int(mu_t.shape[0])
         for k in PARAMS:
             t = getattr(self, k)
@@ -32,10 +36,11 @@ class GaussianScene:
                 raise ValueError(f"{k}: expected {SHAPES[k]} x {n} values, got {tuple(t.shape)}")
 
     @classmethod
-    def from_host(cls, scene, device="cuda"):
+    def from_host(cls, scene, device="cuda", agr=None):
         arrs = scene.arrays() if hasattr(scene, "arrays") else scene
+        w = None if agr is None else torch.as_tensor(np.ascontiguousarray(agr, np.float32)).to(device)
         return cls(*(torch.as_tensor(np.ascontiguousarray(arrs[k], np.float32)).to(device)
-                     for k in PARAMS))
+                     for k in PARAMS), agr=w)
 
     @property
     def n(self) -> int:
@@ -49,7 +54,7 @@ class GaussianScene:
         return 84 * 4 * self.n
 
     def sd7(self) -> L.Sd7Scene:
-        return L.Sd7Scene(*(_ptr(getattr(self, k)) for k in PARAMS), self.n)
+        return L.Sd7Scene(*(_ptr(getattr(self, k)) for k in PARAMS), self.n, _ptr(self.agr))
 
 
 def view_struct(v) -> L.Sd7View:

@@ -238,6 +238,27 @@ def target_image(seed: int, W: int, H: int) -> np.ndarray:
 # Named workloads
 # --------------------------------------------------------------------------
 
+AGR_OUT = (3, 1, 3, 28)      # outputs of the MLPs for mu_p, mu_t, mu_d, the packed L
+AGR_IN, AGR_HIDDEN = 27, 64
+
+
+def agr_weights(seed: int, out_scale=(0.03, 0.03, 0.03, 0.003)) -> np.ndarray:
+    """Random AGR weights (FP32, the packed layout: per MLP p, t, d, l the
+    arrays W1[64][27], b1[64], W2[C_out][64], b2[C_out]).  Drawn in that order
+    from default_rng(seed): W1 ~ N(0, 1/27), b1 ~ N(0, 0.1), W2 ~ N(0, 1/64)
+    and b2 ~ N(0, 0.1), W2 and b2 then scaled by the MLP's out_scale so that
+    the residuals stay small next to the parameters they refine (an untrained
+    network; no trained weights are available)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for c, sc in zip(AGR_OUT, out_scale):
+        parts.append(rng.normal(0.0, np.sqrt(1.0 / AGR_IN), size=AGR_HIDDEN * AGR_IN))
+        parts.append(rng.normal(0.0, 0.1, size=AGR_HIDDEN))
+        parts.append(sc * rng.normal(0.0, np.sqrt(1.0 / AGR_HIDDEN), size=c * AGR_HIDDEN))
+        parts.append(sc * rng.normal(0.0, 0.1, size=c))
+    return np.concatenate(parts).astype(np.float32)
+
+
 def config0(lam: float = 0.05):
     """1,000 Gaussians, one 64x64 view: random unit view direction d, camera at
     -3d looking at the origin, t = 0.5, black background."""

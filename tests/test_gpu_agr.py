@@ -1,0 +1,146 @@
+"""Adaptive Gaussian refinement (Sec. 4.3) on the GPU against the FP64 oracle:
+zero weights reproduce the unrefined path bitwise; random weights give the
+oracle's sliced statistics and images within tolerance; AGR and plain frames
+mix in one batch; the reverse calls refuse AGR scenes."""
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+from tests.gpu_helpers import image_check, slice_tolerance
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+# The MLP runs in FP32: each output is a sum of at most 64 products (after a
+# 7-term first layer), accurate to about 64 x 2^-24 = 4e-6 of the summed
+# magnitudes, which sit below the parameters they refine.  Sliced statistics
+# are compared at 1e-5 of each Gaussian's scale (the unrefined path: 2e-7).
+# The opacity modulation exp(-lambda_t r_t^2 / (2 Sigma_t) - ...) turns an
+# error eps in a refined mean into a relative error s * eps of alpha_c, with
+# s = |d ln alpha_c / d(mu_t, mu_d)|_1 (hundreds for narrow temporal
+# extents); s comes from the FP64 oracle by central differences and eps is
+# taken as EPS_MU.
+AGR_REL = 1e-5
+EPS_MU = 2e-6
+
+
+def log_alpha_sensitivity(ref, view, h=1e-6):
+    """|d ln alpha_c / d mu_t| + sum_k |d ln alpha_c / d mu_d[k]| of the refined
+    scene, by central differences of the oracle's slice."""
+    import copy
+    s = np.zeros(ref.n)
+    for name, k in (("mu_t", None), ("mu_d", 0), ("mu_d", 1), ("mu_d", 2)):
+        lo, hi = copy.copy(ref), copy.copy(ref)
+        for sc, sign in ((lo, -1.0), (hi, 1.0)):
+            arr = np.array(getattr(ref, name), dtype=np.float64, copy=True)
+            if k is None:
+                arr += sign * h
+            else:
+                arr[k] += sign * h
+            setattr(sc, name, arr)
+        a_lo = oracle.slice_(lo, view).alpha_c
+        a_hi = oracle.slice_(hi, view).alpha_c
+        with np.errstate(divide="ignore", invalid="ignore"):
+            d = (np.log(a_hi) - np.log(a_lo)) / (2 * h)
+        s += np.nan_to_num(np.abs(d), nan=0.0, posinf=0.0)
+    return s
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_07946_amd.render import get_renderer
+    return get_renderer(0)
+
+
+def _gs(scene, w=None):
+    from paper_2503_07946_amd.render import GaussianScene
+    return GaussianScene.from_host(scene, agr=w)
+
+
+CASES = {
+    "c0_w7": lambda: (*scenegen.config0(), scenegen.agr_weights(7)),
+    "ragged_72x40_w8": lambda: (scenegen.make_scene(3000, 19, sigma_off=0.15),
+                                scenegen.make_views(1, 19, r=3.0, W=72, H=40, bg=(0.3, 0.2, 0.1)),
+                                scenegen.agr_weights(8)),
+    "corr015_96x64_w9_large": lambda: (scenegen.make_scene(5000, 20, sigma_off=0.15),
+                                       scenegen.make_views(1, 20, r=3.0, W=96, H=64),
+                                       scenegen.agr_weights(9, out_scale=(0.1, 0.1, 0.1, 0.01))),
+}
+
+
+def test_zero_weights_match_the_unrefined_path_bitwise(R):
+    sc, views = scenegen.config0()
+    v = views[0]
+    print("[agr] zero weights vs no AGR", flush=True)
+    a = R.render(_gs(sc), v)
+    b = R.render(_gs(sc, np.zeros(9443, np.float32)), v)
+    torch.cuda.synchronize()
+    for name in ("mu_c", "cov_c", "alpha_c", "splat", "rect", "depth_key"):
+        x = getattr(a, name)(0).cpu().numpy().view(np.uint32)
+        y = getattr(b, name)(0).cpu().numpy().view(np.uint32)
+        assert np.array_equal(x, y), name
+    for name in ("image", "final_T", "last"):
+        assert np.array_equal(getattr(a.frames[0], name).cpu().numpy(), getattr(b.frames[0], name).cpu().numpy())
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_agr_slice_and_image_parity(R, case, report):
+    sc, views, w = CASES[case]()
+    v = views[0]
+    print(f"[agr] {case} n={sc.n} {v.W}x{v.H}", flush=True)
+    b = R.render(_gs(sc, w), v)
+    torch.cuda.synchronize()
+    ora = oracle.slice_(sc, v, agr_weights=w)
+    ref = oracle.agr(sc, v.t, w)
+    ok = ora.status == 0
+    assert ok.mean() > 0.5
+    mscale = np.maximum(np.abs(ora.mu_c).max(0), np.abs(ref.mu_p).max(0))
+    cscale = np.abs(ora.cov_c).max(0)
+    mu = b.mu_c().cpu().numpy().astype(np.float64)
+    cov = b.cov_c().cpu().numpy().astype(np.float64)
+    ac = b.alpha_c().cpu().numpy().astype(np.float64)
+    tol_mu = np.maximum(slice_tolerance(ora.mu_c, mscale), AGR_REL * mscale)
+    tol_cv = np.maximum(slice_tolerance(ora.cov_c, cscale), AGR_REL * cscale)
+    sens = log_alpha_sensitivity(ref, v)
+    tol_ac = np.maximum(slice_tolerance(ora.alpha_c, ora.alpha_c),
+                        (AGR_REL + EPS_MU * sens) * ora.alpha_c)
+    e_mu = (np.abs(mu - ora.mu_c) / np.maximum(mscale, 1e-30))[:, ok].max()
+    e_cv = (np.abs(cov - ora.cov_c) / np.maximum(cscale, 1e-30))[:, ok].max()
+    e_ac = (np.abs(ac - ora.alpha_c) / np.maximum(ora.alpha_c, 1e-30))[ok].max()
+    report("agr_slice_parity", case=case, mu_rel=float(e_mu), cov_rel=float(e_cv), alpha_rel=float(e_ac))
+    assert np.all(np.abs(mu - ora.mu_c)[:, ok] <= tol_mu[:, ok]), e_mu
+    assert np.all(np.abs(cov - ora.cov_c)[:, ok] <= tol_cv[:, ok]), e_cv
+    assert np.all(np.abs(ac - ora.alpha_c)[ok] <= tol_ac[ok]), e_ac
+    img = oracle.render(sc, v, agr_weights=w)
+    err, nflag = image_check(b.frames[0].image.cpu().numpy(), img)
+    report("agr_image_parity", case=case, max_abs=err, flagged=nflag)
+    assert err <= 1e-4, (err, nflag)
+    assert np.abs(img.image - oracle.render(sc, v).image).max() > 1e-3   # the refinement shows
+
+
+def test_agr_and_plain_frames_in_one_batch_equal_alone(R):
+    sA, vA = scenegen.config0()
+    sB = scenegen.make_scene(4000, 21)
+    vB = scenegen.make_views(2, 21, r=3.0, W=80, H=48)
+    gA = _gs(sA, scenegen.agr_weights(3))
+    gB = _gs(sB)
+    items = [(gA, vA[0]), (gB, vB[0]), (gA, vB[1]), (gB, vB[1])]
+    print("[agr] mixed batch of 4", flush=True)
+    mix = R.render_frames(R.make_frames(items))
+    for k, it in enumerate(items):
+        alone = R.render_frames(R.make_frames([it]))
+        for name in ("image", "final_T", "last"):
+            assert np.array_equal(getattr(alone.frames[0], name).cpu().numpy(),
+                                  getattr(mix.frames[k], name).cpu().numpy()), (k, name)
+
+
+def test_reverse_calls_refuse_agr_scenes(R):
+    from paper_2503_07946_amd import _lib as L
+    sc, views = scenegen.config0()
+    b = R.render(_gs(sc, scenegen.agr_weights(3)), views[0])
+    dL = torch.zeros((3, views[0].H, views[0].W), device="cuda")
+    with pytest.raises(L.Sd7Error, match="AGR"):
+        R.backward(b, [dL])
