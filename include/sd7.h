@@ -130,7 +130,10 @@ typedef struct {
 /* A pinhole view at time t (host memory, by value).  R_wc is the row-major
  * world-to-camera rotation (camera axes x right, y down, z forward); c the
  * camera centre; (fx, fy, cx, cy) the intrinsics in pixels; d the view
- * direction the Gaussians are conditioned on; bg the background colour. */
+ * direction the Gaussians are conditioned on (Algorithm 1 takes one d);
+ * bg the background colour.  d_per_gaussian = 1 conditions Gaussian i on
+ * its own direction unit(mu_p,i - c) instead of d (mu_p after refinement
+ * when the scene has AGR weights). */
 typedef struct {
     float R_wc[9];
     float c[3];
@@ -140,10 +143,13 @@ typedef struct {
     float d[3];
     float lambda_t, lambda_d;
     float bg[3];
+    int32_t d_per_gaussian;
 } sd7_view;
 
 /* Gradient outputs of one frame (device, overwritten by the backward):
- * same shapes as the scene arrays; alpha is the activated opacity. */
+ * same shapes as the scene arrays; alpha is the activated opacity.  lambda
+ * (optional, NULL to skip) receives dL/dlambda_t and dL/dlambda_d of the
+ * frame's view, added with atomics: the caller zeroes it. */
 typedef struct {
     float* mu_p;
     float* mu_t;
@@ -151,6 +157,7 @@ typedef struct {
     float* L;
     float* alpha;
     float* sh;
+    float* lambda;
 } sd7_scene_grad;
 
 /* One render request. */

@@ -50,7 +50,7 @@ class OraView(ctypes.Structure):
                 ("W", ctypes.c_int32), ("H", ctypes.c_int32),
                 ("t", ctypes.c_float), ("d", ctypes.c_float * 3),
                 ("lambda_t", ctypes.c_float), ("lambda_d", ctypes.c_float),
-                ("bg", ctypes.c_float * 3)]
+                ("bg", ctypes.c_float * 3), ("d_mode", ctypes.c_int32)]
 
 
 class OraFlagCfg(ctypes.Structure):
@@ -117,6 +117,7 @@ def ora_view(v) -> OraView:
     o.d[:] = [float(x) for x in np.asarray(v.d, np.float32)]
     o.lambda_t, o.lambda_d = v.lambda_t, v.lambda_d
     o.bg[:] = [float(x) for x in np.asarray(v.bg, np.float32)]
+    o.d_mode = 1 if getattr(v, "d_per_gaussian", False) else 0
     return o
 
 

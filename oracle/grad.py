@@ -69,22 +69,31 @@ def sh_basis(x, y, z):
 
 
 def slice_t(P: dict, view):
-    """Conditional mean, covariance (full 3x3) and opacity, Sec. 4.2."""
+    """Conditional mean, covariance (full 3x3) and opacity, Sec. 4.2.  The
+    modulation strengths are P["lambda_t"], P["lambda_d"] when present (so
+    that they can be differentiated), else the view's."""
     n = P["mu_t"].shape[0]
     Ld = (P["L"].T @ _SEL).reshape(n, 7, 7)
     S = Ld @ Ld.transpose(1, 2)
     SPP, SPQ, SQQ = S[:, :3, :3], S[:, :3, 3:], S[:, 3:, 3:]
-    d = torch.tensor(np.asarray(view.d, np.float32), dtype=torch.float64)
-    r = torch.cat([(float(view.t) - P["mu_t"])[:, None], d[None, :] - P["mu_d"].T], dim=1)  # [n,4]
+    if getattr(view, "d_per_gaussian", False):
+        c = torch.tensor(np.asarray(view.c, np.float32), dtype=torch.float64)
+        e = P["mu_p"].T - c[None, :]
+        d = e / torch.sqrt((e * e).sum(1, keepdim=True))              # [n,3]
+    else:
+        d = torch.tensor(np.asarray(view.d, np.float32), dtype=torch.float64)[None, :]
+    r = torch.cat([(float(view.t) - P["mu_t"])[:, None], d - P["mu_d"].T], dim=1)  # [n,4]
+    lam_t = P.get("lambda_t", float(view.lambda_t))
+    lam_d = P.get("lambda_d", float(view.lambda_d))
     Kt = torch.linalg.solve(SQQ, SPQ.transpose(1, 2))          # Sigma_QQ^{-1} Sigma_QP
     mu_c = P["mu_p"].T + (SPQ @ torch.linalg.solve(SQQ, r[:, :, None]))[:, :, 0]
     Sc = SPP - SPQ @ Kt
     Sc = 0.5 * (Sc + Sc.transpose(1, 2))
-    f_t = torch.exp(-0.5 * float(view.lambda_t) * r[:, 0] ** 2 / S[:, 3, 3])
+    f_t = torch.exp(-0.5 * lam_t * r[:, 0] ** 2 / S[:, 3, 3])
     dl = r[:, 1:]
     SDD = S[:, 4:, 4:]
     qd = (dl[:, None, :] @ torch.linalg.solve(SDD, dl[:, :, None]))[:, 0, 0]
-    f_d = torch.exp(-0.5 * float(view.lambda_d) * qd)
+    f_d = torch.exp(-0.5 * lam_d * qd)
     alpha_c = P["alpha"] * f_t * f_d
     return mu_c, Sc, alpha_c
 
@@ -191,12 +200,17 @@ def render_t(P: dict, view, crop=None, chunk_rows: int = 16):
 
 def grad(scene, view, dL_dimage: np.ndarray, crop=None):
     """Vector-Jacobian product of the render with dL_dimage [3,h,w]:
-    returns {param: FP64 gradient array of the parameter's shape}."""
+    returns ({param: FP64 gradient array of the parameter's shape, plus
+    "lambda": [dL/dlambda_t, dL/dlambda_d]}, image)."""
     P = scene_tensors(scene)
+    for k in ("lambda_t", "lambda_d"):
+        P[k] = torch.tensor(float(getattr(view, k)), dtype=torch.float64, requires_grad=True)
     img = render_t(P, view, crop)
     g = torch.tensor(np.asarray(dL_dimage), dtype=torch.float64)
     (img * g).sum().backward()
-    return {k: P[k].grad.numpy().copy() for k in PARAMS}, img.detach().numpy()
+    out = {k: P[k].grad.numpy().copy() for k in PARAMS}
+    out["lambda"] = np.array([float(P["lambda_t"].grad), float(P["lambda_d"].grad)])
+    return out, img.detach().numpy()
 
 
 def l1_grad_image(image: np.ndarray, target: np.ndarray) -> np.ndarray:

@@ -128,10 +128,20 @@ int ora_slice(int64_t n, const double* mu_p, const double* mu_t, const double* m
             for (int j = 0; j < 4; ++j) SQQ[i * 4 + j] = S[3 + i][3 + j];
         if (cholesky(4, SQQ, CQQ) != 0) st |= 2;
 
-        /* r = (t - mu_t, d - mu_d) */
+        /* r = (t - mu_t, d - mu_d); d is the view's, or unit(mu_p - c) */
+        double dg[3] = {d[0], d[1], d[2]};
+        if (v->d_mode) {
+            double e[3], nn = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                e[k] = mu_p[(int64_t)k * n + g] - (double)v->c[k];
+                nn += e[k] * e[k];
+            }
+            nn = sqrt(nn);
+            for (int k = 0; k < 3; ++k) dg[k] = e[k] / nn;
+        }
         double r[4];
         r[0] = t - (double)mu_t[g];
-        for (int k = 0; k < 3; ++k) r[1 + k] = d[k] - (double)mu_d[(int64_t)k * n + g];
+        for (int k = 0; k < 3; ++k) r[1 + k] = dg[k] - (double)mu_d[(int64_t)k * n + g];
 
         /* eq. cond_mean: mu_cond = mu_p + Sigma_PQ Sigma_QQ^{-1} r */
         double w[4] = {r[0], r[1], r[2], r[3]};

@@ -32,6 +32,7 @@ typedef struct {
     float d[3];        /* view direction the Gaussians are conditioned on */
     float lambda_t, lambda_d;
     float bg[3];
+    int32_t d_mode;    /* 1: Gaussian g is conditioned on unit(mu_p,g - c) instead of d */
 } ora_view;
 
 /* Decision bands for flagging pixels whose FP32 result may legitimately

@@ -30,11 +30,13 @@ class Sd7Scene(ctypes.Structure):
 class Sd7View(ctypes.Structure):
     _fields_ = [("R_wc", f32 * 9), ("c", f32 * 3), ("fx", f32), ("fy", f32), ("cx", f32),
                 ("cy", f32), ("W", ctypes.c_int32), ("H", ctypes.c_int32), ("t", f32),
-                ("d", f32 * 3), ("lambda_t", f32), ("lambda_d", f32), ("bg", f32 * 3)]
+                ("d", f32 * 3), ("lambda_t", f32), ("lambda_d", f32), ("bg", f32 * 3),
+                ("d_per_gaussian", ctypes.c_int32)]
 
 
 class Sd7SceneGrad(ctypes.Structure):
-    _fields_ = [("mu_p", P), ("mu_t", P), ("mu_d", P), ("L", P), ("alpha", P), ("sh", P)]
+    _fields_ = [("mu_p", P), ("mu_t", P), ("mu_d", P), ("L", P), ("alpha", P), ("sh", P),
+                ("lambda_", P)]
 
 
 class Sd7Frame(ctypes.Structure):

@@ -131,7 +131,9 @@ __global__ __launch_bounds__(kBlock) void k_agr_slice(const FrameDev* __restrict
 #pragma unroll
         for (int a = 0; a < 3; ++a) mu_d[a] = (double)(x[4 + a] + rd[a]);
         SliceView V;
-        slice_view<false>(S, (double)F.t, F.d, (double)(x[3] + rt[0]), mu_d, F.lambda_t, F.lambda_d, V);
+        double d[3], rn;
+        view_direction(F, mu_p, d, rn);
+        slice_view<false>(S, (double)F.t, d, rn, (double)(x[3] + rt[0]), mu_d, F.lambda_t, F.lambda_d, V);
         float mc[3], cv[6], ac;
         slice_outputs(S, V, mu_p, cv32, cv_fin, F.alpha[i], mc, cv, ac, flag);
         const size_t g0 = F.g0;

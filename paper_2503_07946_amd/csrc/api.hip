@@ -282,6 +282,8 @@ sd7_status upload_table(sd7_ctx* ctx, const sd7_frame* fr, int nf, const Plan& P
         D.image = F.image; D.final_T = F.final_T; D.last = F.last; D.dL_dimage = F.dL_dimage;
         D.g_mu_p = F.grad.mu_p; D.g_mu_t = F.grad.mu_t; D.g_mu_d = F.grad.mu_d;
         D.g_L = F.grad.L; D.g_alpha = F.grad.alpha; D.g_sh = F.grad.sh;
+        D.g_lambda = F.grad.lambda;
+        D.d_mode = F.view.d_per_gaussian ? 1u : 0u;
         D.ncontrib = F.ncontrib;
         D.agr = F.scene.agr;
         D.n = (uint32_t)F.scene.n;

@@ -45,6 +45,7 @@ struct FrameDev {
     float* g_L;
     float* g_alpha;
     float* g_sh;
+    float* g_lambda;     // optional [2]: dL/dlambda_t, dL/dlambda_d (accumulated)
     uint32_t* ncontrib;  // optional per-pixel contributor count
     const float* agr;    // optional AGR weights (SD7_AGR_WEIGHTS floats)
     uint32_t n;        // Gaussians
@@ -53,7 +54,7 @@ struct FrameDev {
     uint32_t tiles_x, tiles_y;
     uint32_t t0;       // first tile in the concatenated tile arrays
     uint32_t nch;      // binning chunks (the kept Gaussians are cut into this many)
-    uint32_t pad0;
+    uint32_t d_mode;   // 1: Gaussian i is conditioned on unit(mu_p,i - c)
     uint32_t m0;       // first entry of the frame's [chunk][tile] count matrix
     float R[9];
     float c[3];

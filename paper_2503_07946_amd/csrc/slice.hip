@@ -44,6 +44,9 @@ struct SliceView {
     double u[4];        // C^{-1} r
     double r[4];
     double y[3];        // Sigma_DD^{-1} delta (reverse pass only)
+    double d[3];        // the direction conditioned on
+    double rn;          // 1 / |mu_p - c| when d = unit(mu_p - c)
+    double q_d;         // delta^T Sigma_DD^{-1} delta
     double e_t, e_d;    // exponents lambda_t r_t^2 / Sigma_t and lambda_d delta^T Sigma_d^{-1} delta
 };
 
@@ -132,14 +135,40 @@ __device__ __forceinline__ void slice_fixed(const double L[28], SliceFixed& S, u
     S.ok = ok;
 }
 
-// mu_t and mu_d of the Gaussian, t and d of the view; y only if WITH_Y.
-template <bool WITH_Y>
-__device__ __forceinline__ void slice_view(const SliceFixed& S, double t, const float d[3], double mu_t,
-                                           const double mu_d[3], float lambda_t, float lambda_d, SliceView& W)
+// The direction Gaussian i is conditioned on: the view's d, or unit(mu_p - c)
+// when the frame asks for one direction per Gaussian (then rn = 1/|mu_p - c|).
+__device__ __forceinline__ void view_direction(const FrameDev& F, const float mu_p[3], double d[3], double& rn)
 {
+    if (F.d_mode) {
+        double e[3], s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            e[k] = (double)mu_p[k] - (double)F.c[k];
+            s = fma(e[k], e[k], s);
+        }
+        rn = 1.0 / sqrt(s);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d[k] = e[k] * rn;
+    } else {
+        rn = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d[k] = (double)F.d[k];
+    }
+}
+
+// mu_t and mu_d of the Gaussian, t of the view, d from view_direction; y only
+// if WITH_Y.
+template <bool WITH_Y>
+__device__ __forceinline__ void slice_view(const SliceFixed& S, double t, const double d[3], double rn,
+                                           double mu_t, const double mu_d[3], float lambda_t, float lambda_d,
+                                           SliceView& W)
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) W.d[k] = d[k];
+    W.rn = rn;
     W.r[0] = t - mu_t;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) W.r[1 + k] = (double)d[k] - mu_d[k];
+    for (int k = 0; k < 3; ++k) W.r[1 + k] = d[k] - mu_d[k];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         double s = W.r[k];
@@ -155,7 +184,8 @@ __device__ __forceinline__ void slice_view(const SliceFixed& S, double t, const 
         for (int m = 0; m < k; ++m) s = fma(-S.CD[k][m], z[m], s);
         z[k] = s * S.rCD[k];
     }
-    W.e_d = (double)lambda_d * (z[0] * z[0] + z[1] * z[1] + z[2] * z[2]);
+    W.q_d = z[0] * z[0] + z[1] * z[1] + z[2] * z[2];
+    W.e_d = (double)lambda_d * W.q_d;
     if (WITH_Y) {
 #pragma unroll
         for (int k = 2; k >= 0; --k) {  // y = CD^{-T} z = Sigma_DD^{-1} delta
@@ -174,10 +204,16 @@ __device__ __forceinline__ void slice_state(const FrameDev& F, uint32_t i, Slice
     const uint32_t n = F.n;
     load_L(F.L, n, i, S.L);
     slice_fixed(S.L, S, flag);
-    double mu_d[3];
+    double mu_d[3], d[3], rn;
 #pragma unroll
     for (int k = 0; k < 3; ++k) mu_d[k] = (double)F.mu_d[(size_t)k * n + i];
-    slice_view<WITH_Y>(S, (double)F.t, F.d, (double)F.mu_t[i], mu_d, F.lambda_t, F.lambda_d, S);
+    float mu_p[3] = {0.f, 0.f, 0.f};
+    if (F.d_mode) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) mu_p[k] = F.mu_p[(size_t)k * n + i];
+    }
+    view_direction(F, mu_p, d, rn);
+    slice_view<WITH_Y>(S, (double)F.t, d, rn, (double)F.mu_t[i], mu_d, F.lambda_t, F.lambda_d, S);
 }
 
 // Sigma_c = Sigma_PP - V V^T (eq. cond_cov), packed (xx, xy, xz, yy, yz, zz),
@@ -274,10 +310,12 @@ __global__ __launch_bounds__(kBlock) void k_slice_bwd(const FrameDev* __restrict
 {
     const int f = frame_of_block(bm, blockIdx.x);
     const FrameDev& F = tab[f];
-    const uint32_t i = (blockIdx.x - bm.start[f]) * kBlock + threadIdx.x;
-    if (i >= F.n) return;
+    const uint32_t i0 = (blockIdx.x - bm.start[f]) * kBlock + threadIdx.x;
+    const bool valid = i0 < F.n;
+    const uint32_t i = valid ? i0 : 0;  // invalid lanes compute on Gaussian 0 and write nothing
     const uint32_t n = F.n;
     const size_t g0 = F.g0;
+    double gl_t = 0.0, gl_d = 0.0;      // this lane's dL/dlambda_t, dL/dlambda_d
     double gm[3], Gc[3][3], ga;
 #pragma unroll
     for (int a = 0; a < 3; ++a) gm[a] = (double)d_mu_c[3 * g0 + (size_t)a * n + i];
@@ -370,6 +408,15 @@ __global__ __launch_bounds__(kBlock) void k_slice_bwd(const FrameDev* __restrict
         GQQ[0][0] += s * 0.5 * lt * S.r[0] * S.r[0] / (S.s_tt * S.s_tt);
 #pragma unroll
         for (int k = 0; k < 3; ++k) out_mu_d[k] += s * ld * S.y[k];
+        // lambda: d ln alpha_c / d lambda_t = -r_t^2 / (2 Sigma_t), / d lambda_d = -q_d / 2
+        gl_t = -0.5 * s * S.r[0] * S.r[0] / S.s_tt;
+        gl_d = -0.5 * s * S.q_d;
+        // d = unit(mu_p - c): dL/dd = -dL/dmu_d, d d / d mu_p = (I - d d^T) / |mu_p - c|
+        if (F.d_mode) {
+            const double dd = -(S.d[0] * out_mu_d[0] + S.d[1] * out_mu_d[1] + S.d[2] * out_mu_d[2]);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) out_mu_p[a] += S.rn * (-out_mu_d[a] - S.d[a] * dd);
+        }
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -391,14 +438,29 @@ __global__ __launch_bounds__(kBlock) void k_slice_bwd(const FrameDev* __restrict
                 dL[tri(a, b)] = 2.0 * acc;
             }
     }
+    if (valid) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) F.g_mu_p[(size_t)a * n + i] = (float)out_mu_p[a];
-    F.g_mu_t[i] = (float)out_mu_t;
+        for (int a = 0; a < 3; ++a) F.g_mu_p[(size_t)a * n + i] = (float)out_mu_p[a];
+        F.g_mu_t[i] = (float)out_mu_t;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) F.g_mu_d[(size_t)a * n + i] = (float)out_mu_d[a];
+        for (int a = 0; a < 3; ++a) F.g_mu_d[(size_t)a * n + i] = (float)out_mu_d[a];
 #pragma unroll
-    for (int k = 0; k < 28; ++k) F.g_L[(size_t)k * n + i] = (float)dL[k];
-    F.g_alpha[i] = (float)out_alpha;
+        for (int k = 0; k < 28; ++k) F.g_L[(size_t)k * n + i] = (float)dL[k];
+        F.g_alpha[i] = (float)out_alpha;
+    } else {
+        gl_t = gl_d = 0.0;
+    }
+    if (F.g_lambda) {  // one atomic per wave and value
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            gl_t += __shfl_xor(gl_t, off);
+            gl_d += __shfl_xor(gl_d, off);
+        }
+        if (__lane_id() == 0) {
+            atomicAdd(&F.g_lambda[0], (float)gl_t);
+            atomicAdd(&F.g_lambda[1], (float)gl_d);
+        }
+    }
 }
 
 }  // namespace sd7

@@ -73,7 +73,9 @@ __global__ __launch_bounds__(kBlock, 3) void k_slice_project(const FrameDev* __r
         if (valid) {
             SliceView W;
             const double md[3] = {(double)mu_d[0], (double)mu_d[1], (double)mu_d[2]};
-            slice_view<false>(S, (double)F.t, F.d, (double)mu_t, md, F.lambda_t, F.lambda_d, W);
+            double d[3], rn;
+            view_direction(F, mu_p, d, rn);
+            slice_view<false>(S, (double)F.t, d, rn, (double)mu_t, md, F.lambda_t, F.lambda_d, W);
             float mc[3], cv[6], ac;
             slice_outputs(S, W, mu_p, cv32, cv_fin, alpha, mc, cv, ac, flag);
             const size_t g0 = F.g0;

@@ -67,6 +67,7 @@ def view_struct(v) -> L.Sd7View:
     s.d[:] = [float(x) for x in np.asarray(v.d, np.float32).reshape(3)]
     s.lambda_t, s.lambda_d = float(v.lambda_t), float(v.lambda_d)
     s.bg[:] = [float(x) for x in np.asarray(v.bg, np.float32).reshape(3)]
+    s.d_per_gaussian = 1 if getattr(v, "d_per_gaussian", False) else 0
     return s
 
 
@@ -212,7 +213,7 @@ class Renderer:
             c.dL_dimage = _ptr(fr.dL_dimage)
             c.ncontrib = _ptr(fr.ncontrib)
             if fr.grads is not None:
-                c.grad = L.Sd7SceneGrad(*(_ptr(fr.grads[k]) for k in PARAMS))
+                c.grad = L.Sd7SceneGrad(*(_ptr(fr.grads[k]) for k in PARAMS), _ptr(fr.grads.get("lambda")))
         return arr
 
     def plan(self, frames, capacity: int) -> L.Sd7Layout:
@@ -275,6 +276,8 @@ class Renderer:
             fr.dL_dimage = g.contiguous()
             if fr.grads is None:
                 fr.grads = {k: torch.empty_like(getattr(fr.scene, k)) for k in PARAMS}
+                fr.grads["lambda"] = torch.empty(2, dtype=torch.float32, device=fr.scene.device)
+            fr.grads["lambda"].zero_()  # dL/dlambda_t, dL/dlambda_d (accumulated)
         b.cstruct = self.cstruct(b.frames)
         for s in ("sd7_rasterize_backward", "sd7_project_backward", "sd7_slice_backward"):
             self.stage(s, b, stream)

@@ -93,6 +93,7 @@ class View:
     lambda_t: float = 0.05
     lambda_d: float = 0.05
     bg: np.ndarray = field(default_factory=lambda: np.zeros(3, np.float32))
+    d_per_gaussian: bool = False   # condition each Gaussian on unit(mu_p - c) instead of d
 
     def replace(self, **kw) -> "View":
         d = dict(self.__dict__)
@@ -110,6 +111,7 @@ class View:
         for k in ("fx", "fy", "cx", "cy", "t", "lambda_t", "lambda_d"):
             setattr(self, k, float(f32(getattr(self, k))))
         self.W, self.H = int(self.W), int(self.H)
+        self.d_per_gaussian = bool(self.d_per_gaussian)
 
 
 def look_at(c, target=(0.0, 0.0, 0.0)) -> np.ndarray:

@@ -34,9 +34,9 @@ def test_exports_every_declared_function(lib):
 
 def test_struct_sizes_match_the_header_layout():
     # sd7_view: 16 floats, 2 int32, t, d[3], 2 lambdas, bg[3] -> 108 bytes
-    assert ctypes.sizeof(L.Sd7View) == 108
+    assert ctypes.sizeof(L.Sd7View) == 112
     assert ctypes.sizeof(L.Sd7Scene) == 64
-    assert ctypes.sizeof(L.Sd7Frame) == 64 + 108 + 4 + 4 * 8 + 6 * 8 + 8  # view padded to 8
+    assert ctypes.sizeof(L.Sd7Frame) == 64 + 112 + 4 * 8 + 7 * 8 + 8
 
 
 def _frame(n=100, W=64, H=48, ptr=0x1000):

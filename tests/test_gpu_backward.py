@@ -53,6 +53,9 @@ CASES = {
     "train_subset_l1": lambda: ("l1",),
     "corr015_ragged": lambda: (scenegen.make_scene(3000, 19, sigma_off=0.15),
                                scenegen.make_views(1, 19, r=3.0, W=72, H=40, bg=(0.3, 0.2, 0.1)), None),
+    "d_per_gaussian_lam03": lambda: (scenegen.make_scene(2500, 23, sigma_off=0.1),
+                                     [v.replace(d_per_gaussian=True, lambda_t=0.3, lambda_d=0.2)
+                                      for v in scenegen.make_views(1, 23, r=3.0, W=64, H=48)], None),
 }
 
 
@@ -80,6 +83,10 @@ def test_gradients_match_oracle(R, case, report):
     dL = (dL * mask[None]).astype(np.float32)     # no gradient through flagged pixels
     g_gpu, _ = _gpu_grad(R, scene, v, dL)
     g_ora, _ = og.grad(scene, v, dL.astype(np.float64))
+    lam_gpu, lam_ora = g_gpu.pop("lambda").astype(np.float64), g_ora.pop("lambda")
+    lam_err = np.abs(lam_gpu - lam_ora) / np.maximum(np.abs(lam_ora), 1e-6 * np.abs(g_ora["alpha"]).sum())
+    report("lambda_grad_parity", case=case, rel=lam_err.tolist(), gpu=lam_gpu.tolist(), oracle=lam_ora.tolist())
+    assert np.all(lam_err <= 1e-3), (lam_gpu, lam_ora)
     rep = _compare(g_gpu, g_ora)
     report("grad_parity", case=case, **{k: {"rel_l2": a, "worst_entry": b} for k, (a, b) in rep.items()})
 

@@ -41,6 +41,9 @@ CASES = {
                                scenegen.make_views(1, 8, r=3.0, W=96, H=80, bg=(0.2, 0.3, 0.4))),
     "corr015_128x72": lambda: (scenegen.make_scene(5000, 9, sigma_off=0.15),
                                scenegen.make_views(1, 9, r=3.0, W=128, H=72)),
+    "d_per_gaussian_80x56": lambda: (scenegen.make_scene(4000, 10, sigma_off=0.1),
+                                     [v.replace(d_per_gaussian=True)
+                                      for v in scenegen.make_views(1, 10, r=3.0, W=80, H=56)]),
 }
 
 
