@@ -227,6 +227,23 @@ typedef struct {
 sd7_status sd7_create(int device, sd7_ctx** out);
 void sd7_destroy(sd7_ctx* ctx);
 
+/* Densification helper (Algorithm 1's optional step; Sec. 4.4): for n
+ * symmetric 3x3 covariances cov[6][n] (packed xx, xy, xz, yy, yz, zz, e.g.
+ * the sliced Sigma_cond planes of a workspace), Sigma = R diag(S^2) R^T with
+ * scale[3][n] = S in descending order (square roots of the eigenvalues, 0
+ * for negative ones) and rot[9][n] = R row-major (plane 3*row + col), its
+ * columns the eigenvectors and det R = +1 (the last column negated when the
+ * decomposition gives -1).  FP64 inside.  Device arrays; asynchronous. */
+sd7_status sd7_cov_decompose(sd7_ctx* ctx, int64_t n, const float* cov, float* scale, float* rot,
+                             sd7_stream stream);
+/* Temporal split test of densification (Sec. 4.4): out[i] = 1 where
+ * |(Sigma_xt, Sigma_yt, Sigma_zt)| > 0.05 * extent and
+ * sqrt(Sigma_t) / time_span > 0.25 for Sigma = L L^T of the scene (the
+ * paper's thresholds; extent is the scene's spatial extent, time_span the
+ * length of the time range), else 0.  FP64 inside.  out: device, n bytes. */
+sd7_status sd7_split_test(sd7_ctx* ctx, const sd7_scene* scene, float extent, float time_span,
+                          uint8_t* out, sd7_stream stream);
+
 /* Message of the last failing call on this host thread ("" if none). */
 const char* sd7_last_error(void);
 

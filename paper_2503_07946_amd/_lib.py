@@ -60,7 +60,8 @@ class Sd7Layout(ctypes.Structure):
 
 STAGES = ("sd7_slice", "sd7_project", "sd7_slice_project", "sd7_bin", "sd7_rasterize", "sd7_render",
           "sd7_rasterize_backward", "sd7_project_backward", "sd7_slice_backward")
-EXPORTS = ("sd7_create", "sd7_destroy", "sd7_last_error", "sd7_plan", "sd7_read_counts") + STAGES
+EXPORTS = ("sd7_create", "sd7_destroy", "sd7_last_error", "sd7_plan", "sd7_read_counts",
+           "sd7_cov_decompose", "sd7_split_test") + STAGES
 
 
 class Sd7Error(RuntimeError):
@@ -103,6 +104,10 @@ def load(path: str = LIB_PATH):
         fn.restype = ctypes.c_int32
     L.sd7_read_counts.argtypes = [P, ctypes.c_int, P, ctypes.POINTER(ctypes.c_uint32), P]
     L.sd7_read_counts.restype = ctypes.c_int32
+    L.sd7_cov_decompose.argtypes = [P, ctypes.c_int64, P, P, P, P]
+    L.sd7_cov_decompose.restype = ctypes.c_int32
+    L.sd7_split_test.argtypes = [P, ctypes.POINTER(Sd7Scene), ctypes.c_float, ctypes.c_float, P, P]
+    L.sd7_split_test.restype = ctypes.c_int32
     _lib = L
     return L
 

@@ -17,6 +17,7 @@
 #include "slice_project.hip"
 #include "bin.hip"
 #include "raster.hip"
+#include "densify.hip"
 
 using namespace sd7;
 
@@ -664,6 +665,38 @@ STAGE(sd7_render, false, {
 STAGE(sd7_rasterize_backward, true, { return do_raster_bwd(c); })
 STAGE(sd7_project_backward, true, { return do_project_bwd(c); })
 STAGE(sd7_slice_backward, true, { return do_slice_bwd(c, frames, nf); })
+
+sd7_status sd7_cov_decompose(sd7_ctx* ctx, int64_t n, const float* cov, float* scale, float* rot,
+                             sd7_stream stream)
+{
+    g_err[0] = 0;
+    if (!ctx) return fail(SD7_EINVAL, "ctx is NULL");
+    if (n < 0 || n >= (int64_t)1 << 31) return fail(SD7_EINVAL, "n=%lld outside [0, 2^31)", (long long)n);
+    if (n == 0) return SD7_OK;
+    if (!cov || !scale || !rot) return fail(SD7_EINVAL, "NULL array");
+    HIP_TRY(hipSetDevice(ctx->device));
+    k_cov_decompose<<<ceil_div(n, kBlock), kBlock, 0, static_cast<hipStream_t>(stream)>>>((uint32_t)n, cov, scale,
+                                                                                          rot);
+    LAUNCH_CHECK("k_cov_decompose");
+    return SD7_OK;
+}
+
+sd7_status sd7_split_test(sd7_ctx* ctx, const sd7_scene* scene, float extent, float time_span, uint8_t* out,
+                          sd7_stream stream)
+{
+    g_err[0] = 0;
+    if (!ctx || !scene) return fail(SD7_EINVAL, "ctx or scene is NULL");
+    const int64_t n = scene->n;
+    if (n < 0 || n >= (int64_t)1 << 31) return fail(SD7_EINVAL, "n=%lld outside [0, 2^31)", (long long)n);
+    if (!(extent > 0.f) || !(time_span > 0.f)) return fail(SD7_EINVAL, "extent and time_span must be > 0");
+    if (n == 0) return SD7_OK;
+    if (!scene->L || !out) return fail(SD7_EINVAL, "NULL array");
+    HIP_TRY(hipSetDevice(ctx->device));
+    k_split_test<<<ceil_div(n, kBlock), kBlock, 0, static_cast<hipStream_t>(stream)>>>((uint32_t)n, scene->L,
+                                                                                       extent, time_span, out);
+    LAUNCH_CHECK("k_split_test");
+    return SD7_OK;
+}
 
 sd7_status sd7_read_counts(sd7_ctx* ctx, int nf, const void* ws, uint32_t* out, sd7_stream stream)
 {

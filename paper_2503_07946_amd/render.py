@@ -287,6 +287,31 @@ class Renderer:
 _RENDERERS: dict = {}
 
 
+def cov_decompose(cov: torch.Tensor, renderer=None):
+    """Densification helper: cov [6, n] (packed symmetric, float32, device) ->
+    (scale [3, n] descending, rot [9, n] row-major R with det R = +1)."""
+    r = renderer or get_renderer(cov.device.index)
+    if cov.dtype != torch.float32 or not cov.is_contiguous() or cov.dim() != 2 or cov.shape[0] != 6:
+        raise ValueError("cov: need a contiguous float32 [6, n] device tensor")
+    n = int(cov.shape[1])
+    scale = torch.empty((3, n), dtype=torch.float32, device=cov.device)
+    rot = torch.empty((9, n), dtype=torch.float32, device=cov.device)
+    st = torch.cuda.current_stream(cov.device)
+    L.check(r.lib.sd7_cov_decompose(r.ctx, n, _ptr(cov), _ptr(scale), _ptr(rot), ctypes.c_void_p(st.cuda_stream)))
+    return scale, rot
+
+
+def split_mask(scene: GaussianScene, extent: float, time_span: float = 1.0, renderer=None) -> torch.Tensor:
+    """Densification helper: bool [n], the Gaussians the temporal split test selects."""
+    r = renderer or get_renderer(scene.device.index)
+    out = torch.empty(scene.n, dtype=torch.uint8, device=scene.device)
+    st = torch.cuda.current_stream(scene.device)
+    s = scene.sd7()
+    L.check(r.lib.sd7_split_test(r.ctx, ctypes.byref(s), float(extent), float(time_span), _ptr(out),
+                                 ctypes.c_void_p(st.cuda_stream)))
+    return out.bool()
+
+
 def get_renderer(device=None) -> Renderer:
     dev = torch.cuda.current_device() if device is None else int(device)
     r = _RENDERERS.get(dev)
