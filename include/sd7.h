@@ -244,6 +244,54 @@ sd7_status sd7_cov_decompose(sd7_ctx* ctx, int64_t n, const float* cov, float* s
 sd7_status sd7_split_test(sd7_ctx* ctx, const sd7_scene* scene, float extent, float time_span,
                           uint8_t* out, sd7_stream stream);
 
+/* ---- training-side helpers (Sec. 4.4: the 3DGS optimizer, pruning at the
+ * raised opacity floor tau_min) ------------------------------------------ */
+
+/* Mutable per-Gaussian arrays in the scene's shapes: parameters, or one of
+ * Adam's moment sets (device, FP32). */
+typedef struct {
+    float* mu_p;
+    float* mu_t;
+    float* mu_d;
+    float* L;
+    float* alpha;
+    float* sh;
+} sd7_arrays;
+
+typedef struct {
+    float lr[6];               /* learning rate per group: mu_p, mu_t, mu_d, L, alpha, sh */
+    float beta1, beta2, eps;   /* Adam */
+    int32_t step;              /* 1 on the first step (bias correction) */
+    float alpha_lo, alpha_hi;  /* the (activated) opacity is kept in [alpha_lo, alpha_hi] */
+    float diag_min;            /* L's diagonal entries are kept >= diag_min */
+} sd7_adam;
+
+/* One Adam step over every parameter value of n Gaussians, in place:
+ * m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * p -= lr / (1 - b1^step) * m / (sqrt(v) / sqrt(1 - b2^step) + eps), then
+ * the opacity and L's diagonal are projected onto their bounds.  m, v start
+ * at zero (the caller's).  grad: the backward's gradient arrays (lambda
+ * unused).  Asynchronous; SD7_EINVAL on NULL arrays, step < 1 or bad betas. */
+sd7_status sd7_adam_step(sd7_ctx* ctx, int64_t n, const sd7_arrays* params, const sd7_scene_grad* grad,
+                         const sd7_arrays* m, const sd7_arrays* v, const sd7_adam* cfg,
+                         sd7_stream stream);
+
+/* Pruning in two calls, with a caller workspace of sd7_prune_workspace_size(n)
+ * bytes (256-byte aligned).  sd7_prune_count marks the Gaussians with
+ * alpha >= tau and writes their number to *d_kept (device); the caller then
+ * allocates arrays for that many Gaussians and sd7_prune_apply copies, for
+ * each of narrays arrays of planes[j] planes ([planes][n] -> [planes][n_kept]),
+ * the kept Gaussians in their order (at most 32 arrays, e.g. a scene's six
+ * parameter arrays and Adam's moments); with n_kept = 0 it copies nothing
+ * and the array pointers may be NULL.  The workspace must hold the state of
+ * the count call with the same alpha.  Asynchronous. */
+size_t sd7_prune_workspace_size(int64_t n);
+sd7_status sd7_prune_count(sd7_ctx* ctx, int64_t n, const float* alpha, float tau, void* ws,
+                           size_t ws_bytes, uint32_t* d_kept, sd7_stream stream);
+sd7_status sd7_prune_apply(sd7_ctx* ctx, int64_t n, int64_t n_kept, const float* const* src,
+                           float* const* dst, const int32_t* planes, int narrays, const void* ws,
+                           size_t ws_bytes, sd7_stream stream);
+
 /* Message of the last failing call on this host thread ("" if none). */
 const char* sd7_last_error(void);
 

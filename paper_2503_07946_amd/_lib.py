@@ -39,6 +39,15 @@ class Sd7SceneGrad(ctypes.Structure):
                 ("lambda_", P)]
 
 
+class Sd7Arrays(ctypes.Structure):
+    _fields_ = [("mu_p", P), ("mu_t", P), ("mu_d", P), ("L", P), ("alpha", P), ("sh", P)]
+
+
+class Sd7Adam(ctypes.Structure):
+    _fields_ = [("lr", f32 * 6), ("beta1", f32), ("beta2", f32), ("eps", f32), ("step", ctypes.c_int32),
+                ("alpha_lo", f32), ("alpha_hi", f32), ("diag_min", f32)]
+
+
 class Sd7Frame(ctypes.Structure):
     _fields_ = [("scene", Sd7Scene), ("view", Sd7View), ("image", P), ("final_T", P),
                 ("last", P), ("dL_dimage", P), ("grad", Sd7SceneGrad), ("ncontrib", P)]
@@ -61,7 +70,8 @@ class Sd7Layout(ctypes.Structure):
 STAGES = ("sd7_slice", "sd7_project", "sd7_slice_project", "sd7_bin", "sd7_rasterize", "sd7_render",
           "sd7_rasterize_backward", "sd7_project_backward", "sd7_slice_backward")
 EXPORTS = ("sd7_create", "sd7_destroy", "sd7_last_error", "sd7_plan", "sd7_read_counts",
-           "sd7_cov_decompose", "sd7_split_test") + STAGES
+           "sd7_cov_decompose", "sd7_split_test", "sd7_adam_step", "sd7_prune_workspace_size",
+           "sd7_prune_count", "sd7_prune_apply") + STAGES
 
 
 class Sd7Error(RuntimeError):
@@ -108,6 +118,16 @@ def load(path: str = LIB_PATH):
     L.sd7_cov_decompose.restype = ctypes.c_int32
     L.sd7_split_test.argtypes = [P, ctypes.POINTER(Sd7Scene), ctypes.c_float, ctypes.c_float, P, P]
     L.sd7_split_test.restype = ctypes.c_int32
+    L.sd7_adam_step.argtypes = [P, ctypes.c_int64, ctypes.POINTER(Sd7Arrays), ctypes.POINTER(Sd7SceneGrad),
+                                ctypes.POINTER(Sd7Arrays), ctypes.POINTER(Sd7Arrays), ctypes.POINTER(Sd7Adam), P]
+    L.sd7_adam_step.restype = ctypes.c_int32
+    L.sd7_prune_workspace_size.argtypes = [ctypes.c_int64]
+    L.sd7_prune_workspace_size.restype = ctypes.c_size_t
+    L.sd7_prune_count.argtypes = [P, ctypes.c_int64, P, ctypes.c_float, P, ctypes.c_size_t, P, P]
+    L.sd7_prune_count.restype = ctypes.c_int32
+    L.sd7_prune_apply.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(P), ctypes.POINTER(P),
+                                  ctypes.POINTER(ctypes.c_int32), ctypes.c_int, P, ctypes.c_size_t, P]
+    L.sd7_prune_apply.restype = ctypes.c_int32
     _lib = L
     return L
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -18,6 +19,7 @@
 #include "bin.hip"
 #include "raster.hip"
 #include "densify.hip"
+#include "optim.hip"
 
 using namespace sd7;
 
@@ -359,18 +361,39 @@ sd7_status fill(const Call& c, void* p, size_t count, uint32_t value)
 
 // Exclusive scan in place; the length is host-known (len_dev null) or read on
 // the device.  The grand total lands in partials[ntiles] and *total_out.
+// part: at least max_len / kScanItems + 4 entries.
+sd7_status scan_with(hipStream_t st, uint32_t* part, uint32_t* data, uint32_t len_host, const uint32_t* len_dev,
+                     uint32_t max_len, uint32_t* total_out)
+{
+    const uint32_t blocks = std::max(1u, std::min<uint32_t>(ceil_div(max_len, kScanItems), kPersistentBlocks));
+    k_scan_reduce<<<blocks, 256, 0, st>>>(data, len_host, len_dev, part);
+    LAUNCH_CHECK("k_scan_reduce");
+    k_scan_spine<<<1, 1024, 0, st>>>(part, len_host, len_dev, total_out);
+    LAUNCH_CHECK("k_scan_spine");
+    k_scan_down<<<blocks, 256, 0, st>>>(data, data, len_host, len_dev, part);
+    LAUNCH_CHECK("k_scan_down");
+    return SD7_OK;
+}
+
 sd7_status scan(const Call& c, uint32_t* data, uint32_t len_host, const uint32_t* len_dev, uint32_t max_len,
                 uint32_t* total_out)
 {
-    uint32_t* part = c.at<uint32_t>(c.P.S.partials);
-    const uint32_t blocks = std::max(1u, std::min<uint32_t>(ceil_div(max_len, kScanItems), kPersistentBlocks));
-    k_scan_reduce<<<blocks, 256, 0, c.st>>>(data, len_host, len_dev, part);
-    LAUNCH_CHECK("k_scan_reduce");
-    k_scan_spine<<<1, 1024, 0, c.st>>>(part, len_host, len_dev, total_out);
-    LAUNCH_CHECK("k_scan_spine");
-    k_scan_down<<<blocks, 256, 0, c.st>>>(data, data, len_host, len_dev, part);
-    LAUNCH_CHECK("k_scan_down");
-    return SD7_OK;
+    return scan_with(c.st, c.at<uint32_t>(c.P.S.partials), data, len_host, len_dev, max_len, total_out);
+}
+
+// Pruning workspace: keep flags [n], their exclusive scan [n], scan partials.
+struct PruneWs {
+    size_t keep, pos, part, bytes;
+};
+PruneWs prune_ws(int64_t n)
+{
+    PruneWs w;
+    size_t off = 0;
+    w.keep = off; off = align_up(off + 4 * (size_t)n);
+    w.pos = off;  off = align_up(off + 4 * (size_t)n);
+    w.part = off; off = align_up(off + 4 * ((size_t)n / kScanItems + 8));
+    w.bytes = off;
+    return w;
 }
 
 sd7_status radix_pass(const Call& c, bool first, const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
@@ -695,6 +718,110 @@ sd7_status sd7_split_test(sd7_ctx* ctx, const sd7_scene* scene, float extent, fl
     k_split_test<<<ceil_div(n, kBlock), kBlock, 0, static_cast<hipStream_t>(stream)>>>((uint32_t)n, scene->L,
                                                                                        extent, time_span, out);
     LAUNCH_CHECK("k_split_test");
+    return SD7_OK;
+}
+
+sd7_status sd7_adam_step(sd7_ctx* ctx, int64_t n, const sd7_arrays* params, const sd7_scene_grad* grad,
+                         const sd7_arrays* m, const sd7_arrays* v, const sd7_adam* cfg, sd7_stream stream)
+{
+    g_err[0] = 0;
+    if (!ctx || !params || !grad || !m || !v || !cfg) return fail(SD7_EINVAL, "NULL argument");
+    if (n < 0 || n >= (int64_t)1 << 31) return fail(SD7_EINVAL, "n=%lld outside [0, 2^31)", (long long)n);
+    if (cfg->step < 1) return fail(SD7_EINVAL, "step=%d must be >= 1", cfg->step);
+    if (!(cfg->beta1 >= 0.f && cfg->beta1 < 1.f && cfg->beta2 >= 0.f && cfg->beta2 < 1.f && cfg->eps > 0.f))
+        return fail(SD7_EINVAL, "need 0 <= beta1, beta2 < 1 and eps > 0");
+    if (n == 0) return SD7_OK;
+    ArraySet P, G, M, V;
+    const float* gp[6] = {grad->mu_p, grad->mu_t, grad->mu_d, grad->L, grad->alpha, grad->sh};
+    float* pp[6] = {params->mu_p, params->mu_t, params->mu_d, params->L, params->alpha, params->sh};
+    float* mp[6] = {m->mu_p, m->mu_t, m->mu_d, m->L, m->alpha, m->sh};
+    float* vp[6] = {v->mu_p, v->mu_t, v->mu_d, v->L, v->alpha, v->sh};
+    for (int k = 0; k < 6; ++k) {
+        if (!gp[k] || !pp[k] || !mp[k] || !vp[k]) return fail(SD7_EINVAL, "NULL array in group %d", k);
+        P.a[k] = pp[k]; G.a[k] = const_cast<float*>(gp[k]); M.a[k] = mp[k]; V.a[k] = vp[k];
+    }
+    AdamArgs a;
+    for (int k = 0; k < 6; ++k) a.lr[k] = cfg->lr[k];
+    a.beta1 = cfg->beta1; a.beta2 = cfg->beta2; a.eps = cfg->eps;
+    a.rbc1 = (float)(1.0 / (1.0 - std::pow((double)cfg->beta1, cfg->step)));
+    a.rsbc2 = (float)(1.0 / std::sqrt(1.0 - std::pow((double)cfg->beta2, cfg->step)));
+    a.alpha_lo = cfg->alpha_lo; a.alpha_hi = cfg->alpha_hi; a.diag_min = cfg->diag_min;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const uint64_t total = 84ull * (uint64_t)n;
+    k_adam<<<(uint32_t)((total + kBlock - 1) / kBlock), kBlock, 0, static_cast<hipStream_t>(stream)>>>(
+        (uint32_t)n, P, G, M, V, a);
+    LAUNCH_CHECK("k_adam");
+    return SD7_OK;
+}
+
+size_t sd7_prune_workspace_size(int64_t n)
+{
+    return n < 0 ? 0 : prune_ws(n).bytes;
+}
+
+sd7_status sd7_prune_count(sd7_ctx* ctx, int64_t n, const float* alpha, float tau, void* ws, size_t ws_bytes,
+                           uint32_t* d_kept, sd7_stream stream)
+{
+    g_err[0] = 0;
+    if (!ctx || !d_kept || !ws) return fail(SD7_EINVAL, "NULL argument");
+    if (n < 0 || n >= (int64_t)1 << 31) return fail(SD7_EINVAL, "n=%lld outside [0, 2^31)", (long long)n);
+    const PruneWs w = prune_ws(n);
+    if (ws_bytes < w.bytes) return fail(SD7_EWORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, w.bytes);
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(SD7_EINVAL, "workspace not 256-byte aligned");
+    if (n > 0 && !alpha) return fail(SD7_EINVAL, "alpha is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(ws);
+    uint32_t* keep = reinterpret_cast<uint32_t*>(base + w.keep);
+    uint32_t* pos = reinterpret_cast<uint32_t*>(base + w.pos);
+    if (n == 0) {
+        k_prune_total<<<1, 64, 0, st>>>(0, keep, pos, d_kept);
+        LAUNCH_CHECK("k_prune_total");
+        return SD7_OK;
+    }
+    k_prune_flags<<<ceil_div(n, kBlock), kBlock, 0, st>>>((uint32_t)n, alpha, tau, keep, pos);
+    LAUNCH_CHECK("k_prune_flags");
+    sd7_status s = scan_with(st, reinterpret_cast<uint32_t*>(base + w.part), pos, (uint32_t)n, nullptr,
+                             (uint32_t)n, nullptr);
+    if (s != SD7_OK) return s;
+    k_prune_total<<<1, 64, 0, st>>>((uint32_t)n, keep, pos, d_kept);
+    LAUNCH_CHECK("k_prune_total");
+    return SD7_OK;
+}
+
+sd7_status sd7_prune_apply(sd7_ctx* ctx, int64_t n, int64_t n_kept, const float* const* src, float* const* dst,
+                           const int32_t* planes, int narrays, const void* ws, size_t ws_bytes, sd7_stream stream)
+{
+    g_err[0] = 0;
+    if (!ctx || !ws || (narrays > 0 && (!src || !dst || !planes))) return fail(SD7_EINVAL, "NULL argument");
+    if (n < 0 || n >= (int64_t)1 << 31 || n_kept < 0 || n_kept > n)
+        return fail(SD7_EINVAL, "need 0 <= n_kept <= n < 2^31");
+    if (narrays < 0 || narrays > kMaxPruneArrays) return fail(SD7_EINVAL, "narrays=%d outside [0, %d]", narrays,
+                                                              kMaxPruneArrays);
+    const PruneWs w = prune_ws(n);
+    if (ws_bytes < w.bytes) return fail(SD7_EWORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, w.bytes);
+    if (n == 0 || n_kept == 0) return SD7_OK;  // nothing to copy (arrays may be empty)
+    PruneArrays pa;
+    std::memset(&pa, 0, sizeof(pa));
+    pa.narrays = narrays;
+    uint64_t tot = 0;
+    for (int j = 0; j < narrays; ++j) {
+        if (!src[j] || !dst[j] || planes[j] < 1) return fail(SD7_EINVAL, "array %d: NULL or planes < 1", j);
+        pa.src[j] = src[j];
+        pa.dst[j] = dst[j];
+        pa.plane0[j] = (uint32_t)tot;
+        tot += (uint64_t)planes[j];
+    }
+    pa.plane0[narrays] = (uint32_t)tot;
+    if (tot == 0) return SD7_OK;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const char* base = static_cast<const char*>(ws);
+    const uint32_t chunks = ceil_div(n, kBlock);
+    if (tot * chunks >= (1ull << 31)) return fail(SD7_EINVAL, "too many planes x Gaussians");
+    k_prune_apply<<<(uint32_t)(tot * chunks), kBlock, 0, static_cast<hipStream_t>(stream)>>>(
+        (uint32_t)n, (uint32_t)n_kept, chunks, reinterpret_cast<const uint32_t*>(base + w.keep),
+        reinterpret_cast<const uint32_t*>(base + w.pos), pa);
+    LAUNCH_CHECK("k_prune_apply");
     return SD7_OK;
 }
 

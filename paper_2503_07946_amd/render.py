@@ -312,6 +312,71 @@ def split_mask(scene: GaussianScene, extent: float, time_span: float = 1.0, rend
     return out.bool()
 
 
+class Adam:
+    """Fused Adam over a scene's six parameter arrays (sd7_adam_step) and
+    pruning at an opacity floor (sd7_prune_count / sd7_prune_apply).
+
+    The learning rates are per group; the defaults follow 3DGS's schedule at
+    its start where a group has a counterpart (position 1.6e-4 for the three
+    means, SH 2.5e-3) and are readings for the others: the paper keeps the
+    3DGS settings and names none for mu_t, mu_d or the factor L, and this
+    library renders the activated opacity instead of a logit."""
+
+    DEFAULT_LR = {"mu_p": 1.6e-4, "mu_t": 1.6e-4, "mu_d": 1.6e-4, "L": 1e-3, "alpha": 1e-2, "sh": 2.5e-3}
+
+    def __init__(self, scene: GaussianScene, lr=None, betas=(0.9, 0.999), eps=1e-15,
+                 alpha_bounds=(1e-4, 0.9999), diag_min=1e-4, renderer=None):
+        self.r = renderer or get_renderer(scene.device.index)
+        self.lr = dict(self.DEFAULT_LR, **(lr or {}))
+        self.betas, self.eps, self.alpha_bounds, self.diag_min = betas, eps, alpha_bounds, diag_min
+        self.m = {k: torch.zeros_like(getattr(scene, k)) for k in PARAMS}
+        self.v = {k: torch.zeros_like(getattr(scene, k)) for k in PARAMS}
+        self.t = 0
+
+    @staticmethod
+    def _arrays(d) -> L.Sd7Arrays:
+        return L.Sd7Arrays(*(_ptr(d[k]) for k in PARAMS))
+
+    def step(self, scene: GaussianScene, grads: dict):
+        self.t += 1
+        cfg = L.Sd7Adam()
+        cfg.lr[:] = [float(self.lr[k]) for k in PARAMS]
+        cfg.beta1, cfg.beta2 = float(self.betas[0]), float(self.betas[1])
+        cfg.eps, cfg.step = float(self.eps), self.t
+        cfg.alpha_lo, cfg.alpha_hi = float(self.alpha_bounds[0]), float(self.alpha_bounds[1])
+        cfg.diag_min = float(self.diag_min)
+        p = self._arrays({k: getattr(scene, k) for k in PARAMS})
+        g = L.Sd7SceneGrad(*(_ptr(grads[k]) for k in PARAMS), None)
+        st = torch.cuda.current_stream(scene.device)
+        L.check(self.r.lib.sd7_adam_step(self.r.ctx, scene.n, ctypes.byref(p), ctypes.byref(g),
+                                         ctypes.byref(self._arrays(self.m)), ctypes.byref(self._arrays(self.v)),
+                                         ctypes.byref(cfg), ctypes.c_void_p(st.cuda_stream)))
+
+    def prune(self, scene: GaussianScene, tau: float = 0.01) -> GaussianScene:
+        """The Gaussians with opacity >= tau (the paper's tau_min = 0.01), with
+        their moments; one host read of the kept count."""
+        n, dev = scene.n, scene.device
+        lib = self.r.lib
+        ws = torch.empty(max(int(lib.sd7_prune_workspace_size(n)), 256), dtype=torch.uint8, device=dev)
+        cnt = torch.zeros(1, dtype=torch.int32, device=dev)
+        st = torch.cuda.current_stream(dev)
+        L.check(lib.sd7_prune_count(self.r.ctx, n, _ptr(scene.alpha), float(tau), _ptr(ws), ws.numel(),
+                                    _ptr(cnt), ctypes.c_void_p(st.cuda_stream)))
+        k = int(cnt.item())
+        srcs = [getattr(scene, p) for p in PARAMS] + [self.m[p] for p in PARAMS] + [self.v[p] for p in PARAMS]
+        dsts = [torch.empty(SHAPES[p] * k, dtype=torch.float32, device=dev).view(*(
+                (SHAPES[p], k) if getattr(scene, p).dim() == 2 else (k,))) for p in PARAMS] * 3
+        dsts = [torch.empty_like(d) for d in dsts]
+        planes = (ctypes.c_int32 * len(srcs))(*[SHAPES[p] for p in PARAMS] * 3)
+        sp = (ctypes.c_void_p * len(srcs))(*[t.data_ptr() for t in srcs])
+        dp = (ctypes.c_void_p * len(dsts))(*[t.data_ptr() for t in dsts])
+        L.check(lib.sd7_prune_apply(self.r.ctx, n, k, sp, dp, planes, len(srcs), _ptr(ws), ws.numel(),
+                                    ctypes.c_void_p(st.cuda_stream)))
+        self.m = dict(zip(PARAMS, dsts[6:12]))
+        self.v = dict(zip(PARAMS, dsts[12:18]))
+        return GaussianScene(*dsts[:6], agr=scene.agr)
+
+
 def get_renderer(device=None) -> Renderer:
     dev = torch.cuda.current_device() if device is None else int(device)
     r = _RENDERERS.get(dev)
