@@ -86,22 +86,8 @@ __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab,
     const uint2 rg = ranges[F.t0 + tile];
     const float4* __restrict__ rec = splat + (size_t)F.g0 * 3;
     const uint32_t gmax = __builtin_amdgcn_readfirstlane(F.n - 1);  // pairs exist only if n > 0
-    // The record of the next splat and the index of the one after it are
-    // loaded while a splat is blended.  Past the list's end the loads repeat
-    // its last entry (in bounds, unused); indices are clamped where used.
-    Splat s{};
-    uint32_t g1 = 0;  // index of the splat after s
-    if (rg.x < rg.y) {
-        s = load_splat(rec, min(pair_g[rg.x], gmax));
-        g1 = pair_g[min(rg.x + 1, rg.y - 1)];
-    }
-    for (uint32_t e = rg.x; e < rg.y; ++e) {
-        if (((e - rg.x) & 7) == 0 &&
-            __ballot(fminf(fminf(fy[0], fy[1]), fminf(fy[2], fy[3])) < kFar) == 0)
-            break;
-        const Splat sn = load_splat(rec, min(g1, gmax));
-        const uint32_t g2 = pair_g[min(e + 2, rg.y - 1)];
-        asm volatile("" ::: "memory");  // keep the loads ahead of the blend (no wait here)
+    // Blend one splat (list entry e) into the lane's four pixels.
+    auto blend = [&](const Splat& s, uint32_t e) {
         float dx, Bdx, dy[4], p[4];
         splat_exponents(s, fx, fy, dx, Bdx, dy, p);
 #pragma unroll
@@ -123,8 +109,35 @@ __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab,
                 last[k] = stop ? e - rg.x : last[k];
             }
         }
-        s = sn;
-        g1 = g2;
+    };
+    // Two splat records in scalar registers, even and odd entries: while one
+    // is blended the other is being loaded.  Scalar loads complete out of
+    // order and are waited for all at once, so each load is issued right
+    // after the wait for the record the next blend uses; past the list's end
+    // the loads repeat its last entry (in bounds, unused); indices are
+    // clamped where used.
+    const uint32_t eend = rg.y - 1;
+    Splat s0{}, s1{};
+    uint32_t gi = 0;  // index of the next entry to load
+    if (rg.x < rg.y) {
+        s0 = load_splat(rec, min(pair_g[rg.x], gmax));
+        gi = pair_g[min(rg.x + 1, eend)];
+    }
+    for (uint32_t e = rg.x; e < rg.y; e += 2) {
+        if (((e - rg.x) & 7) == 0 &&
+            __ballot(fminf(fminf(fy[0], fy[1]), fminf(fy[2], fy[3])) < kFar) == 0)
+            break;
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): s0 and gi are in
+        s1 = load_splat(rec, min(gi, gmax));         // entry e + 1
+        uint32_t gn = pair_g[min(e + 2, eend)];
+        asm volatile("" ::: "memory");  // keep the loads ahead of the blend
+        blend(s0, e);
+        if (e + 1 >= rg.y) break;
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // s1 and gn are in
+        s0 = load_splat(rec, min(gn, gmax));         // entry e + 2
+        gi = pair_g[min(e + 3, eend)];
+        asm volatile("" ::: "memory");
+        blend(s1, e + 1);
     }
     const size_t plane = (size_t)F.W * F.H;
 #pragma unroll
