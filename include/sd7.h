@@ -183,7 +183,7 @@ typedef struct {
  *   off_cov_c    float  [6 planes]             conditional covariance (xx,xy,xz,yy,yz,zz)
  *   off_alpha_c  float  [1 plane]              conditional opacity
  *   off_splat    float  [Ntot][12]             per Gaussian (AoS): u, v, A, B, C, lo,
- *                                              r, g, b, depth, alpha_c, 0 where
+ *                                              r, g, b, 16 C, alpha_c, depth where
  *                                              (A, B, C) = -log2(e) (a/2, b, c/2) for the
  *                                              conic q = a dx^2 + 2b dx dy + c dy^2 and
  *                                              lo = log2(alpha_c), so that

@@ -170,9 +170,10 @@ __device__ __forceinline__ bool project_emit(const FrameDev& F, uint32_t i, floa
     float4* rec = splat + (g0 + i) * 3;
     if (keep) {
         // exponent of alpha in base 2: A dx^2 + B dx dy + C dy^2 + log2(alpha_c)
+        const float C = kNegHalfLog2e * p.c;
         rec[0] = make_float4(p.u, p.v, kNegHalfLog2e * p.a, kNegLog2e * p.b);
-        rec[1] = make_float4(kNegHalfLog2e * p.c, log2f(ac), rgb[0], rgb[1]);
-        rec[2] = make_float4(rgb[2], p.x[2], ac, 0.f);
+        rec[1] = make_float4(C, log2f(ac), rgb[0], rgb[1]);
+        rec[2] = make_float4(rgb[2], 16.0f * C, ac, p.x[2]);
     } else {
         rec[0] = make_float4(0.f, 0.f, 0.f, 0.f);
         rec[1] = make_float4(0.f, 0.f, 0.f, 0.f);

@@ -15,19 +15,21 @@
 // (A, B, C) = -(a, 2b, c) log2(e) / 2 and lo = log2(alpha_c):
 //   p = A dx^2 + B dx dy + C dy^2 + lo          (= log2 of alpha_c e^{-q/2})
 //   the splat counts at the pixel iff p >= log2(1/255);
-//   alpha = min(0.99, 2^p); w = T alpha; T' = T - w;
+//   alpha = min(0.99, 2^p); w = T alpha; T' = T - T alpha;
 //   stop before the splat if T' < 1e-4, else C += rgb w, T = T'.
-// The forward and reverse kernels evaluate these with the same explicit
-// fused operations, so they take the same decisions.
+// p is evaluated in full at the lane's first row only and carried down its
+// four rows by forward differences of the quadratic (the record holds 16 C
+// for that).  The forward and reverse kernels evaluate all of this with the
+// same explicit fused operations, so they take the same decisions.
 #include "common.h"
 
 namespace sd7 {
 
 constexpr float kLog2AlphaMin = -7.99435343685886f;  // log2(1/255)
-constexpr float kFar = 1e30f;                         // sample row of a finished pixel
+constexpr float kFar = 1e30f;                         // opacity threshold of a finished pixel
 
 struct Splat {
-    float u, v, A, B, C, lo, r, g, b;
+    float u, v, A, B, C, lo, r, g, b, C16;
 };
 
 __device__ __forceinline__ Splat load_splat(const float4* __restrict__ rec, uint32_t g)
@@ -35,24 +37,30 @@ __device__ __forceinline__ Splat load_splat(const float4* __restrict__ rec, uint
     const float4 p0 = rec[3 * (size_t)g];
     const float4 p1 = rec[3 * (size_t)g + 1];
     const float4 p2 = rec[3 * (size_t)g + 2];
-    return Splat{p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x};
+    return Splat{p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x, p2.y};
 }
 
 __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 
-// log2 of the splat's opacity at the lane's four pixels (sample column fx,
-// sample rows fy[k]); also returns dx, B dx and the row offsets dy.
-__device__ __forceinline__ void splat_exponents(const Splat& s, float fx, const float fy[4], float& dx,
-                                                float& Bdx, float dy[4], float p[4])
+// log2 of the splat's opacity at the lane's four pixels: sample column fx,
+// sample rows fy0 + 4k.  With dy0 = v - fy0 the rows are dy0 - 4k, and
+//   p_{k+1} - p_k = -4 (2 C dy0 + B dx) + 16 C (2k + 1).
+// Also returns dx, B dx and dy0.
+__device__ __forceinline__ void splat_exponents(const Splat& s, float fx, float fy0, float& dx,
+                                                float& Bdx, float& dy0, float p[4])
 {
     dx = s.u - fx;
     const float base = fmaf(s.A * dx, dx, s.lo);
     Bdx = s.B * dx;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        dy[k] = s.v - fy[k];
-        p[k] = fmaf(dy[k], fmaf(s.C, dy[k], Bdx), base);
-    }
+    dy0 = s.v - fy0;
+    const float in0 = fmaf(s.C, dy0, Bdx);
+    p[0] = fmaf(dy0, in0, base);
+    float D = fmaf(fmaf(s.C, dy0, in0), -4.0f, s.C16);
+    p[1] = p[0] + D;
+    D = fmaf(s.C16, 2.0f, D);
+    p[2] = p[1] + D;
+    D = fmaf(s.C16, 2.0f, D);
+    p[3] = p[2] + D;
 }
 
 template <bool COUNT>
@@ -68,16 +76,16 @@ __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab,
     const uint32_t lane = threadIdx.x;
     const uint32_t px = tx * kTile + (lane & 15);
     const uint32_t py0 = ty * kTile + (lane >> 4);  // band k: row py0 + 4k
-    const float fx = (float)px + 0.5f;
-    // A pixel that has stopped (or lies outside the image) moves its sample
-    // row to kFar: its exponent becomes -inf there (C < 0), so it never
+    const float fx = (float)px + 0.5f, fy0 = (float)py0 + 0.5f;
+    // th[k] is the pixel's opacity threshold, log2(1/255); a pixel that has
+    // stopped (or lies outside the image) raises it to kFar, so it never
     // passes the opacity test again and needs no flag of its own.
-    float fy[4], T[4], C0[4], C1[4], C2[4];
+    float th[4], T[4], C0[4], C1[4], C2[4];
     uint32_t last[4], ncon[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const uint32_t py = py0 + 4 * k;
-        fy[k] = (px < F.W && py < F.H) ? (float)py + 0.5f : kFar;
+        th[k] = (px < F.W && py < F.H) ? kLog2AlphaMin : kFar;
         T[k] = 1.0f;
         C0[k] = C1[k] = C2[k] = 0.0f;
         last[k] = 0;
@@ -88,24 +96,31 @@ __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab,
     const uint32_t gmax = __builtin_amdgcn_readfirstlane(F.n - 1);  // pairs exist only if n > 0
     // Blend one splat (list entry e) into the lane's four pixels.
     auto blend = [&](const Splat& s, uint32_t e) {
-        float dx, Bdx, dy[4], p[4];
-        splat_exponents(s, fx, fy, dx, Bdx, dy, p);
+        float dx, Bdx, dy0, p[4];
+        splat_exponents(s, fx, fy0, dx, Bdx, dy0, p);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const bool pass = p[k] >= kLog2AlphaMin;
+            const bool pass = p[k] >= th[k];
             if (__ballot(pass) == 0) continue;  // the splat reaches no pixel of band k
             const float alpha = pass ? fminf(kAlphaMax, exp2_fast(p[k])) : 0.0f;
             const float w = T[k] * alpha;
-            const float Tn = fmaf(-T[k], alpha, T[k]);
-            const bool stop = Tn < kTMin;  // only a passing pixel can stop: T >= kTMin before
-            const float wc = stop ? 0.0f : w;
-            C0[k] = fmaf(s.r, wc, C0[k]);
-            C1[k] = fmaf(s.g, wc, C1[k]);
-            C2[k] = fmaf(s.b, wc, C2[k]);
-            T[k] = stop ? T[k] : Tn;
-            if (COUNT) ncon[k] += (pass && !stop) ? 1u : 0u;
-            if (__ballot(stop)) {  // once per pixel: it has consumed the entries before e
-                fy[k] = stop ? kFar : fy[k];
+            T[k] = fmaf(-T[k], alpha, T[k]);
+            C0[k] = fmaf(s.r, w, C0[k]);
+            C1[k] = fmaf(s.g, w, C1[k]);
+            C2[k] = fmaf(s.b, w, C2[k]);
+            if (COUNT) ncon[k] += pass ? 1u : 0u;
+            // Only a passing pixel can stop (T >= 1e-4 before).  Once per
+            // pixel: take this splat's blend back (T to at least 1e-4, so
+            // the pixel cannot stop again) and retire the pixel, which has
+            // consumed the entries before e.
+            const bool stop = T[k] < kTMin;
+            if (__ballot(stop)) {
+                T[k] = stop ? fmaxf(T[k] + w, kTMin) : T[k];
+                C0[k] = stop ? fmaf(-s.r, w, C0[k]) : C0[k];
+                C1[k] = stop ? fmaf(-s.g, w, C1[k]) : C1[k];
+                C2[k] = stop ? fmaf(-s.b, w, C2[k]) : C2[k];
+                if (COUNT) ncon[k] -= stop ? 1u : 0u;
+                th[k] = stop ? kFar : th[k];
                 last[k] = stop ? e - rg.x : last[k];
             }
         }
@@ -125,7 +140,7 @@ __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab,
     }
     for (uint32_t e = rg.x; e < rg.y; e += 2) {
         if (((e - rg.x) & 7) == 0 &&
-            __ballot(fminf(fminf(fy[0], fy[1]), fminf(fy[2], fy[3])) < kFar) == 0)
+            __ballot(fminf(fminf(th[0], th[1]), fminf(th[2], th[3])) < kFar) == 0)
             break;
         __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): s0 and gi are in
         s1 = load_splat(rec, min(gi, gmax));         // entry e + 1
@@ -149,7 +164,7 @@ __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab,
             F.image[plane + pix] = C1[k] + T[k] * F.bg[1];
             F.image[2 * plane + pix] = C2[k] + T[k] * F.bg[2];
             F.final_T[pix] = T[k];
-            F.last[pix] = fy[k] < kFar ? rg.y - rg.x : last[k];  // a pixel that never stopped used all
+            F.last[pix] = th[k] < kFar ? rg.y - rg.x : last[k];  // a pixel that never stopped used all
             if (COUNT && F.ncontrib) F.ncontrib[pix] = ncon[k];
         }
     }
@@ -205,15 +220,14 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const FrameDev* __restrict__ 
     const uint32_t lane = threadIdx.x;
     const uint32_t px = tx * kTile + (lane & 15);
     const uint32_t py0 = ty * kTile + (lane >> 4);  // band k: row py0 + 4k
-    const float fx = (float)px + 0.5f;
+    const float fx = (float)px + 0.5f, fy0 = (float)py0 + 0.5f;
     const size_t plane = (size_t)F.W * F.H;
-    float fy[4], T[4], Co[4][3], gC[4][3], acc[4][3];
+    float T[4], Co[4][3], gC[4][3], acc[4][3];
     uint32_t last[4];
     uint32_t lmax = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const uint32_t py = py0 + 4 * k;
-        fy[k] = (float)py + 0.5f;
         T[k] = 1.0f;
         last[k] = 0;
 #pragma unroll
@@ -239,8 +253,8 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const FrameDev* __restrict__ 
         const uint32_t g = min(pair_g[e], gmax);
         const Splat s = load_splat(rec, g);
         const uint32_t pos = e - rg.x;
-        float dx, Bdx, dyv[4], p[4];
-        splat_exponents(s, fx, fy, dx, Bdx, dyv, p);
+        float dx, Bdx, dy0, p[4];
+        splat_exponents(s, fx, fy0, dx, Bdx, dy0, p);
         bool pass[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) pass[k] = pos < last[k] && p[k] >= kLog2AlphaMin;
@@ -264,9 +278,10 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const FrameDev* __restrict__ 
             const float ga = T[k] * dot_rgb - dot_s * inv;
             const float sk = (con && raw < kAlphaMax) ? ga * alpha : 0.0f;
             S0 += sk;
-            const float sdy = sk * dyv[k];
+            const float dy = dy0 - 4.0f * k;
+            const float sdy = sk * dy;
             S1 += sdy;
-            S2 = fmaf(sdy, dyv[k], S2);
+            S2 = fmaf(sdy, dy, S2);
             Sr = fmaf(wc, gC[k][0], Sr);
             Sg = fmaf(wc, gC[k][1], Sg);
             Sb = fmaf(wc, gC[k][2], Sb);

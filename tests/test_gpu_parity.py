@@ -89,7 +89,8 @@ def test_project_parity(R, case):
     np.testing.assert_allclose(sp[both, 10], sl.alpha_c[both], rtol=1e-6)
     np.testing.assert_allclose(2.0 ** sp[both, 5], sl.alpha_c[both], rtol=2e-6)
     np.testing.assert_allclose(sp[both, 6:9].T, pr.rgb[:, both], atol=2e-6)
-    np.testing.assert_allclose(sp[both, 9], pr.depth[both], rtol=1e-6)
+    np.testing.assert_allclose(sp[both, 11], pr.depth[both], rtol=1e-6)
+    assert np.array_equal(sp[both, 9], 16.0 * sp[both, 4])  # the band step's coefficient
 
 
 @pytest.mark.parametrize("case", list(CASES))
