@@ -188,7 +188,16 @@ typedef struct {
  *                                              conic q = a dx^2 + 2b dx dy + c dy^2 and
  *                                              lo = log2(alpha_c), so that
  *                                              alpha_c e^{-q/2} = 2^(A dx^2 + B dx dy + C dy^2 + lo)
- *   off_rect     uint32 [Ntot][2]              tile box: (x0 | y0 << 16, x1 | y1 << 16), x1, y1 exclusive
+ *   off_rect     uint32 [Ntot][4]              tile footprint: the tile box (x0 | y0 << 16,
+ *                                              x1 | y1 << 16; x1, y1 exclusive), then row
+ *                                              trims: word 2 for box rows 0..3, word 3 for
+ *                                              rows m..m+3 (m = h - 4 if the box has h > 8
+ *                                              rows, else 4), one byte per row, low nibble =
+ *                                              tiles dropped at the row's left end, high
+ *                                              nibble = at its right end; other rows whole.
+ *                                              Row r then spans tiles [x0 + lo, x1 - hi).
+ *                                              A dropped tile holds no pixel where the
+ *                                              splat reaches alpha >= 1/255.
  *   off_depth_key uint32 [Ntot]                float bits of depth; 0xFFFFFFFF = culled
  *   off_order    uint32 [Ntot]                 frame-local indices of kept Gaussians in
  *                                              (depth, index) order; entries >= kept unused

@@ -60,7 +60,7 @@ struct Scratch {
     size_t sk_a, sv_a, sk_b;         // depth sort ping-pong (keys a, vals a, keys b)
     size_t pt_a, pt_b, pg_b;         // radix tile sort: tile keys and ping-pong buffers
     size_t toff;                     // tile offsets (scan of tiles per sorted Gaussian)
-    size_t srect;                    // tile boxes in depth order (counting binner)
+    size_t srect;                    // footprints in depth order (counting binner)
     size_t segs_all, segs_kept, segs_pairs;
     size_t tot_all, tot_kept, tot_pairs;
     size_t hist, partials, words;
@@ -215,7 +215,7 @@ sd7_status make_plan(const sd7_frame* fr, int nf, int64_t cap, Plan& P, bool nee
     L.off_cov_c = take(4 * 6 * N);
     L.off_alpha_c = take(4 * N);
     L.off_splat = take(4 * kSplatFloats * N);
-    L.off_rect = take(8 * N);
+    L.off_rect = take(16 * N);
     L.off_depth_key = take(4 * N);
     L.off_order = take(4 * N);
     L.off_pair_g = take(4 * C);
@@ -235,7 +235,7 @@ sd7_status make_plan(const sd7_frame* fr, int nf, int64_t cap, Plan& P, bool nee
     S.pt_b = take(4 * CR);
     S.pg_b = take(4 * CR);
     S.toff = take(4 * (N + 16));
-    S.srect = take(8 * (P.counting ? N : 0));
+    S.srect = take(16 * (P.counting ? N : 0));
     S.segs_all = take(sizeof(SortSeg) * nf);
     S.segs_kept = take(sizeof(SortSeg) * nf);
     S.segs_pairs = take(sizeof(SortSeg) * nf);
@@ -437,7 +437,7 @@ sd7_status do_project(const Call& c)
     if (c.P.gblocks == 0) return SD7_OK;
     k_project<<<c.P.gblocks, kBlock, 0, c.st>>>(c.tab, c.P.gmap, c.at<float>(L.off_mu_c), c.at<float>(L.off_cov_c),
                                                  c.at<float>(L.off_alpha_c), c.at<float4>(L.off_splat),
-                                                 c.at<uint2>(L.off_rect), c.at<uint32_t>(L.off_depth_key), c.counts);
+                                                 c.at<uint4>(L.off_rect), c.at<uint32_t>(L.off_depth_key), c.counts);
     LAUNCH_CHECK("k_project");
     return SD7_OK;
 }
@@ -455,7 +455,7 @@ sd7_status do_slice_project(const Call& c)
     if (s != SD7_OK || c.P.sblocks == 0) return s;
     k_slice_project<<<c.P.sblocks, kBlock, 0, c.st>>>(
         c.tab, c.P.sgrp, c.at<float>(L.off_mu_c), c.at<float>(L.off_cov_c), c.at<float>(L.off_alpha_c),
-        c.at<float4>(L.off_splat), c.at<uint2>(L.off_rect), c.at<uint32_t>(L.off_depth_key), c.counts);
+        c.at<float4>(L.off_splat), c.at<uint4>(L.off_rect), c.at<uint32_t>(L.off_depth_key), c.counts);
     LAUNCH_CHECK("k_slice_project");
     return SD7_OK;
 }
@@ -490,8 +490,8 @@ sd7_status do_bin(const Call& c)
     uint32_t* toff = c.at<uint32_t>(S.toff);
     if (c.P.gblocks) {
         k_gather_ntiles<<<c.P.gblocks, kBlock, 0, c.st>>>(c.tab, c.P.gmap, c.counts, order,
-                                                          c.at<uint2>(L.off_rect), toff,
-                                                          c.P.counting ? c.at<uint2>(S.srect) : nullptr);
+                                                          c.at<uint4>(L.off_rect), toff,
+                                                          c.P.counting ? c.at<uint4>(S.srect) : nullptr);
         LAUNCH_CHECK("k_gather_ntiles");
     }
     const uint32_t ntot = (uint32_t)L.n_total;
@@ -505,7 +505,7 @@ sd7_status do_bin(const Call& c)
         // tile totals -> scan of the totals -> placement -> ranges
         uint32_t* cnt = c.at<uint32_t>(c.P.cnt);
         uint32_t* ttot = c.at<uint32_t>(c.P.ttot);
-        const uint2* srect = c.at<uint2>(S.srect);
+        const uint4* srect = c.at<uint4>(S.srect);
         const uint32_t ttiles = (uint32_t)L.tiles_total;
         if (c.P.kblocks) {
             k_tile_count<<<c.P.kblocks, 256, sizeof(uint32_t) * c.P.max_tiles, c.st>>>(c.tab, c.P.kmap, c.counts,
@@ -536,7 +536,7 @@ sd7_status do_bin(const Call& c)
     const uint32_t mwp = c.P.max_wt_pairs;
     if (L.pair_capacity > 0) {
         const uint32_t blocks = std::min<uint32_t>(mwp, kPersistentBlocks);
-        k_emit<<<blocks, 256, 0, c.st>>>(c.tab, c.counts, order, c.at<uint2>(L.off_rect), toff, segs_pairs, nf,
+        k_emit<<<blocks, 256, 0, c.st>>>(c.tab, c.counts, order, c.at<uint4>(L.off_rect), toff, segs_pairs, nf,
                                          tot_pairs, ct, cg);
         LAUNCH_CHECK("k_emit");
         for (int p = 0; p < passes; ++p) {

@@ -3,7 +3,8 @@
 //      Gaussians by the bits of their FP32 depth (positive floats order like
 //      their bit patterns), values = frame-local Gaussian index; the first
 //      pass also drops culled Gaussians (compaction).
-//   2. exclusive scan of the tiles each sorted Gaussian touches -> pair offsets.
+//   2. exclusive scan of the tiles of each sorted Gaussian's footprint -> pair
+//      offsets.
 //   3. emit: every output pair (tile, Gaussian) is written by one lane
 //      (load-balanced over pairs, not over Gaussians), staged in LDS and
 //      stored coalesced; pairs come out in depth order.
@@ -304,15 +305,15 @@ __global__ void k_setup_depth(const FrameDev* __restrict__ tab, int nf, const ui
     tot_kept->wt = wt_kept; tot_kept->hist_len = 256u * wt_kept;
 }
 
-// Tiles touched by each Gaussian in depth order (0 past the kept ones) and,
-// when srect is given, the tile boxes themselves in depth order (empty boxes
+// Tiles of each Gaussian's footprint in depth order (0 past the kept ones)
+// and, when srect is given, the footprints themselves in depth order (empty
 // past the kept ones).
 __global__ __launch_bounds__(kBlock) void k_gather_ntiles(const FrameDev* __restrict__ tab, BlockMap bm,
                                                           const uint32_t* __restrict__ counts,
                                                           const uint32_t* __restrict__ order,
-                                                          const uint2* __restrict__ rect,
+                                                          const uint4* __restrict__ rect,
                                                           uint32_t* __restrict__ ntiles,
-                                                          uint2* __restrict__ srect)
+                                                          uint4* __restrict__ srect)
 {
     const int f = frame_of_block(bm, blockIdx.x);
     const FrameDev& F = tab[f];
@@ -320,10 +321,10 @@ __global__ __launch_bounds__(kBlock) void k_gather_ntiles(const FrameDev* __rest
     if (j >= F.n) return;
     const uint32_t kept = counts[f * SD7_CNT_WORDS + SD7_CNT_KEPT];
     uint32_t nt = 0;
-    uint2 r = make_uint2(0u, 0u);
+    uint4 r = make_uint4(0u, 0u, 0u, 0u);
     if (j < kept) {
         r = rect[F.g0 + order[F.g0 + j]];
-        nt = ((r.y & 0xFFFFu) - (r.x & 0xFFFFu)) * ((r.y >> 16) - (r.x >> 16));
+        nt = Footprint(r).tiles();
     }
     ntiles[F.g0 + j] = nt;
     if (srect) srect[F.g0 + j] = r;
@@ -369,11 +370,40 @@ __global__ void k_setup_pairs(const FrameDev* __restrict__ tab, int nf, uint32_t
     tot->hist_len = 256u * wt;
 }
 
+// Tile id of the l-th tile of a footprint (row by row, left to right);
+// l < tiles().
+__device__ __forceinline__ uint32_t footprint_tile(const Footprint& fp, uint32_t l, uint32_t tiles_x)
+{
+    const uint32_t h = fp.h(), m = fp.first_bottom_row(), w = fp.w();
+    int a, b;
+    for (uint32_t r = 0; r < 4 && r < h; ++r) {
+        const uint32_t n = fp.row_tiles(r);
+        if (l < n) {
+            fp.row(r, a, b);
+            return (fp.y0 + r) * tiles_x + (uint32_t)a + l;
+        }
+        l -= n;
+    }
+    if (m > 4) {  // whole rows 4 .. m-1
+        const uint32_t mid = (m - 4) * w;
+        if (l < mid) return (fp.y0 + 4 + l / w) * tiles_x + fp.x0 + l % w;
+        l -= mid;
+    }
+    uint32_t r = m;
+    for (; r + 1 < h; ++r) {
+        const uint32_t n = fp.row_tiles(r);
+        if (l < n) break;
+        l -= n;
+    }
+    fp.row(r, a, b);
+    return (fp.y0 + r) * tiles_x + (uint32_t)a + l;
+}
+
 // Load-balanced emission: work tile w covers pairs [k*4096, (k+1)*4096) of
 // one frame; each lane finds the Gaussian of its first pair by binary search
 // over the pair offsets and walks forward.
 __global__ __launch_bounds__(256) void k_emit(const FrameDev* __restrict__ tab, const uint32_t* __restrict__ counts,
-                                              const uint32_t* __restrict__ order, const uint2* __restrict__ rect,
+                                              const uint32_t* __restrict__ order, const uint4* __restrict__ rect,
                                               const uint32_t* __restrict__ toff,
                                               const SortSeg* __restrict__ segs, int nseg,
                                               const SortTotals* __restrict__ tot,
@@ -404,7 +434,7 @@ __global__ __launch_bounds__(256) void k_emit(const FrameDev* __restrict__ tab, 
             uint32_t j = a;
             uint32_t start = tf[j] - lo;
             uint32_t next = (j + 1 < kept) ? tf[j + 1] - lo : sg.len;
-            uint2 rc = rect[F.g0 + of[j]];
+            uint4 rc = rect[F.g0 + of[j]];
             uint32_t g = of[j];
 #pragma unroll 1
             for (int r = 0; r < 16; ++r) {
@@ -417,10 +447,7 @@ __global__ __launch_bounds__(256) void k_emit(const FrameDev* __restrict__ tab, 
                     g = of[j];
                     rc = rect[F.g0 + g];
                 }
-                const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, wdt = (rc.y & 0xFFFFu) - x0;
-                const uint32_t l = o - start;
-                const uint32_t ty = y0 + l / wdt, tx = x0 + l % wdt;
-                s_t[threadIdx.x * 16 + r] = ty * F.tiles_x + tx;
+                s_t[threadIdx.x * 16 + r] = footprint_tile(Footprint(rc), o - start, F.tiles_x);
                 s_g[threadIdx.x * 16 + r] = g;
             }
         }
@@ -465,8 +492,8 @@ __global__ __launch_bounds__(256) void k_ranges(const FrameDev* __restrict__ tab
 // so the runs of one tile follow each other in depth order.  k_group_place
 // then runs one wave per (chunk, group of 8 x 8 tiles), one lane per tile: it
 // scans the chunk's boxes in depth order, visits those that meet the group
-// one at a time, and every lane whose tile the box covers appends the
-// Gaussian to its run.  Each tile list thus comes out in (depth, index) order
+// one at a time, and every lane whose tile the Gaussian's footprint holds
+// appends the Gaussian to its run.  Each tile list thus comes out in (depth, index) order
 // without a sort over pairs, and every wave writes only its own 64 runs.
 // ---------------------------------------------------------------------------
 
@@ -488,11 +515,11 @@ constexpr int kBinAhead = 4;
 
 // One block (256 lanes) per (frame, chunk) writes the chunk's row of the
 // count matrix (zeros for a frame whose pairs overflowed).  Per-row difference
-// array over the frame's tiles in LDS: a box [x0, x1) x [y0, y1) adds +1 at
-// (x0, y) and -1 at (x1, y) of each of its rows.
+// array over the frame's tiles in LDS: a footprint whose row y spans tiles
+// [a, b) adds +1 at (a, y) and -1 at (b, y).
 __global__ __launch_bounds__(256) void k_tile_count(const FrameDev* __restrict__ tab, BlockMap cm,
                                                     const uint32_t* __restrict__ counts,
-                                                    const uint2* __restrict__ srect,
+                                                    const uint4* __restrict__ srect,
                                                     uint32_t* __restrict__ cnt)
 {
     extern __shared__ uint32_t s_d[];
@@ -508,11 +535,21 @@ __global__ __launch_bounds__(256) void k_tile_count(const FrameDev* __restrict__
     const uint32_t j0 = chunk_begin(kept, F.nch, c), j1 = chunk_begin(kept, F.nch, c + 1);
     if (live) {
         for (uint32_t j = j0 + threadIdx.x; j < j1; j += 256) {
-            const uint2 r = srect[F.g0 + j];
-            const uint32_t x0 = r.x & 0xFFFFu, y0 = r.x >> 16, x1 = r.y & 0xFFFFu, y1 = r.y >> 16;
-            for (uint32_t y = y0; y < y1; ++y) {
-                atomicAdd(&s_d[y * tx + x0], 1u);
-                if (x1 < tx) atomicSub(&s_d[y * tx + x1], 1u);
+            const Footprint fp(srect[F.g0 + j]);
+            if (!fp.trimmed()) {
+                for (uint32_t y = fp.y0; y < fp.y1; ++y) {
+                    atomicAdd(&s_d[y * tx + fp.x0], 1u);
+                    if (fp.x1 < tx) atomicSub(&s_d[y * tx + fp.x1], 1u);
+                }
+                continue;
+            }
+            for (uint32_t r = 0; r < fp.h(); ++r) {
+                int a, b;
+                fp.row(r, a, b);
+                if (a >= b) continue;
+                const uint32_t y = fp.y0 + r;
+                atomicAdd(&s_d[y * tx + a], 1u);
+                if ((uint32_t)b < tx) atomicSub(&s_d[y * tx + b], 1u);
             }
         }
     }
@@ -538,7 +575,7 @@ __global__ __launch_bounds__(256) void k_tile_count(const FrameDev* __restrict__
 __global__ __launch_bounds__(64) void k_group_place(const FrameDev* __restrict__ tab, BlockMap cm,
                                                     const uint32_t* __restrict__ counts,
                                                     const uint32_t* __restrict__ order,
-                                                    const uint2* __restrict__ srect,
+                                                    const uint4* __restrict__ srect,
                                                     const uint32_t* __restrict__ cnt_pre,
                                                     const uint32_t* __restrict__ tstart,
                                                     uint32_t* __restrict__ pair_g)
@@ -565,16 +602,16 @@ __global__ __launch_bounds__(64) void k_group_place(const FrameDev* __restrict__
         const uint32_t* ts = tstart + F.t0;
         if (valid) slot = cf[SD7_CNT_PAIR_BASE] + (ts[t] - ts[0]) + cnt_pre[F.m0 + (size_t)c * T + t];
     }
-    const uint2* rf = srect + F.g0;
+    const uint4* rf = srect + F.g0;
     const uint32_t* of = order + F.g0;
     // the boxes and indices of the next kBinAhead x 64 Gaussians are loaded
     // while the current ones are visited; empty boxes past j1
-    uint2 rn[kBinAhead];
+    uint4 rn[kBinAhead];
     uint32_t gn[kBinAhead];
 #pragma unroll
     for (int k = 0; k < kBinAhead; ++k) {
         const uint32_t jj = j0 + k * 64 + lane;
-        rn[k] = make_uint2(0u, 0u);
+        rn[k] = make_uint4(0u, 0u, 0u, 0u);
         gn[k] = 0;
         if (jj < j1) {
             rn[k] = rf[jj];
@@ -582,14 +619,14 @@ __global__ __launch_bounds__(64) void k_group_place(const FrameDev* __restrict__
         }
     }
     for (uint32_t j = j0; j < j1; j += kBinAhead * 64) {
-        uint2 r[kBinAhead];
+        uint4 r[kBinAhead];
         uint32_t g[kBinAhead];
 #pragma unroll
         for (int k = 0; k < kBinAhead; ++k) {
             r[k] = rn[k];
             g[k] = gn[k];
             const uint32_t jj = j + (kBinAhead + k) * 64 + lane;
-            rn[k] = make_uint2(0u, 0u);
+            rn[k] = make_uint4(0u, 0u, 0u, 0u);
             if (jj < j1) {
                 rn[k] = rf[jj];
                 gn[k] = of[jj];
@@ -604,11 +641,15 @@ __global__ __launch_bounds__(64) void k_group_place(const FrameDev* __restrict__
             while (m) {  // the meeting boxes in depth order
                 const int p = __builtin_ctzll(m);
                 m &= m - 1;
-                const uint32_t rx = __builtin_amdgcn_readlane(r[k].x, p);
-                const uint32_t ry = __builtin_amdgcn_readlane(r[k].y, p);
+                const Footprint fp(make_uint4(__builtin_amdgcn_readlane(r[k].x, p),
+                                              __builtin_amdgcn_readlane(r[k].y, p),
+                                              __builtin_amdgcn_readlane(r[k].z, p),
+                                              __builtin_amdgcn_readlane(r[k].w, p)));
                 const uint32_t gp = __builtin_amdgcn_readlane(g[k], p);
-                const uint32_t qx0 = rx & 0xFFFFu, qy0 = rx >> 16;
-                const bool hit = valid && (lx - qx0) < ((ry & 0xFFFFu) - qx0) && (ly - qy0) < ((ry >> 16) - qy0);
+                const uint32_t row = ly - fp.y0;  // wraps above the box
+                int a = (int)fp.x0, b = (int)fp.x1;
+                if (fp.trimmed()) fp.row(row, a, b);  // uniform branch
+                const bool hit = valid && row < fp.h() && (int)lx >= a && (int)lx < b;
                 if (hit) pair_g[slot++] = gp;
             }
         }

@@ -119,6 +119,52 @@ __device__ __forceinline__ bool project_one(const FrameDev& F, const float m[3],
     return true;
 }
 
+// Row trims of a footprint (the layout is described with Footprint): for the
+// tile rows it stores, the tiles at either end of the row that the ellipse
+// q <= k misses.  q is evaluated through the 2D covariance: at row offset dy
+// the ellipse spans dx = dy s01 / s11 +- sqrt((k - dy^2 / s11) det / s11); on
+// a tile row's strip of dy the left end is least at the clamp of the leftmost
+// point's dy into the strip, the right end greatest at the clamp of the
+// rightmost point's.  k is raised by 1/16 of itself plus 1/4, which covers the
+// hardware square root and reciprocal used here and the rasterizer's FP32
+// exponent; a box one tile wide or high, or an ill-conditioned covariance,
+// gets no trims.
+__device__ __forceinline__ uint2 footprint_trims(const Proj& p, float k, uint32_t rx0, uint32_t ry0, uint32_t rx1,
+                                                 uint32_t ry1)
+{
+    const uint32_t w = rx1 - rx0, h = ry1 - ry0;
+    const float tr = p.s00 + p.s11;
+    if (w < 2 || h < 2 || !(tr * tr < 1e6f * p.det)) return make_uint2(0u, 0u);
+    const uint32_t m = h > 8 ? h - 4 : 4;  // first of the bottom rows
+    const uint32_t nrow = min(h, 8u);
+    const float km = fmaf(k, 1.0625f, 0.25f);
+    const float r11 = __builtin_amdgcn_rcpf(p.s11);
+    const float slope = p.s01 * r11, wsq = p.det * r11;
+    const float dyx = p.s01 * __builtin_amdgcn_sqrtf(km * __builtin_amdgcn_rcpf(p.s00));  // rightmost point; leftmost at -dyx
+    const float hy = __builtin_amdgcn_sqrtf(km * p.s11);
+    const float inv_tile = 1.0f / (float)kTile;
+    uint32_t word[2] = {0u, 0u};
+    for (uint32_t q = 0; q < nrow; ++q) {
+        const uint32_t r = q < 4 ? q : m + (q - 4);
+        const float y = (float)((ry0 + r) * kTile) - p.v;
+        const float dya = fmaxf(y, -hy), dyb = fminf(y + (float)kTile, hy);
+        const float yl = fminf(fmaxf(-dyx, dya), dyb), yr = fminf(fmaxf(dyx, dya), dyb);
+        const float xl = fmaf(slope, yl, p.u) - __builtin_amdgcn_sqrtf(fmaxf(fmaf(-yl * r11, yl, km), 0.0f) * wsq);
+        const float xr = fmaf(slope, yr, p.u) + __builtin_amdgcn_sqrtf(fmaxf(fmaf(-yr * r11, yr, km), 0.0f) * wsq);
+        // tiles left of the one holding xl and right of the one holding xr; a
+        // strip that misses the ellipse empties the row (as far as 15 + 15
+        // tiles go); NaN keeps the row whole (fmaxf returns the other operand)
+        float lt = fminf(fmaxf(floorf(xl * inv_tile) - (float)rx0, 0.0f), 15.0f);
+        float rt = fminf(fmaxf((float)(rx1 - 1) - floorf(xr * inv_tile), 0.0f), 15.0f);
+        if (!(dya <= dyb)) {
+            lt = fminf((float)w, 15.0f);
+            rt = fminf((float)w - lt, 15.0f);
+        }
+        word[q >> 2] |= ((uint32_t)lt | (uint32_t)rt << 4) << (8 * (q & 3));
+    }
+    return make_uint2(word[0], word[1]);
+}
+
 // SH coefficient j = 3k + ch of Gaussian i, read from the scene.
 struct ShGlobal {
     const float* __restrict__ sh;
@@ -132,12 +178,13 @@ struct ShGlobal {
 template <class Sh>
 __device__ __forceinline__ bool project_emit(const FrameDev& F, uint32_t i, float ac, const float m[3],
                                              const float cv[6], const Sh& sh, float4* __restrict__ splat,
-                                             uint2* __restrict__ rect, uint32_t* __restrict__ depth_key)
+                                             uint4* __restrict__ rect, uint32_t* __restrict__ depth_key)
 {
     const size_t g0 = F.g0;
     Proj p;
     bool keep = ac >= kAlphaMin && project_one(F, m, cv, p);
     uint32_t rx0 = 0, ry0 = 0, rx1 = 0, ry1 = 0;
+    uint2 trims = make_uint2(0u, 0u);
     if (keep) {
         const float k = 2.0f * logf(ac / kAlphaMin);
         const float hx = sqrtf(k * p.s00), hy = sqrtf(k * p.s11);
@@ -151,6 +198,7 @@ __device__ __forceinline__ bool project_emit(const FrameDev& F, uint32_t i, floa
         if (keep) {
             rx0 = (uint32_t)tx0; ry0 = (uint32_t)ty0;
             rx1 = (uint32_t)tx1 + 1; ry1 = (uint32_t)ty1 + 1;
+            trims = footprint_trims(p, k, rx0, ry0, rx1, ry1);
         }
     }
     float rgb[3] = {0.f, 0.f, 0.f};
@@ -179,7 +227,7 @@ __device__ __forceinline__ bool project_emit(const FrameDev& F, uint32_t i, floa
         rec[1] = make_float4(0.f, 0.f, 0.f, 0.f);
         rec[2] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    rect[g0 + i] = make_uint2(rx0 | (ry0 << 16), rx1 | (ry1 << 16));
+    rect[g0 + i] = make_uint4(rx0 | (ry0 << 16), rx1 | (ry1 << 16), trims.x, trims.y);
     depth_key[g0 + i] = keep ? __float_as_uint(p.x[2]) : kCulled;
     return keep;
 }
@@ -193,7 +241,7 @@ __device__ __forceinline__ void wave_kept(bool keep, uint32_t* __restrict__ coun
 __global__ __launch_bounds__(kBlock) void k_project(const FrameDev* __restrict__ tab, BlockMap bm,
                                                     const float* __restrict__ mu_c, const float* __restrict__ cov_c,
                                                     const float* __restrict__ alpha_c, float4* __restrict__ splat,
-                                                    uint2* __restrict__ rect, uint32_t* __restrict__ depth_key,
+                                                    uint4* __restrict__ rect, uint32_t* __restrict__ depth_key,
                                                     uint32_t* __restrict__ counts)
 {
     const int f = frame_of_block(bm, blockIdx.x);

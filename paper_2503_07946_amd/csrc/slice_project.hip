@@ -26,7 +26,7 @@ struct ShLds {
 __global__ __launch_bounds__(kBlock, 3) void k_slice_project(const FrameDev* __restrict__ tab, SceneGroups sg,
                                                           float* __restrict__ mu_c, float* __restrict__ cov_c,
                                                           float* __restrict__ alpha_c, float4* __restrict__ splat,
-                                                          uint2* __restrict__ rect, uint32_t* __restrict__ depth_key,
+                                                          uint4* __restrict__ rect, uint32_t* __restrict__ depth_key,
                                                           uint32_t* __restrict__ counts)
 {
     const uint32_t lb = xcd_contiguous(blockIdx.x, gridDim.x);

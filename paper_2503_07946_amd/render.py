@@ -123,7 +123,7 @@ class Batch:
 
     def rect(self, f=0):
         n = self.frames[f].scene.n
-        return self._arr(self.layout.off_rect, torch.int32, 2 * n, 2 * self.g0(f)).view(n, 2)
+        return self._arr(self.layout.off_rect, torch.int32, 4 * n, 4 * self.g0(f)).view(n, 4)
 
     def depth_key(self, f=0):
         n = self.frames[f].scene.n

@@ -9,25 +9,39 @@ import oracle
 CULLED = 0xFFFFFFFF
 
 
+def footprint_rows(rect: np.ndarray):
+    """Rows of tile footprints [n, 4] (box, then row trims: word 2 for box rows
+    0..3, word 3 for rows m..m+3 with m = h - 4 when h > 8 else 4; byte = left
+    | right << 4).  Returns, per (footprint, box row) in footprint-major,
+    row-major order: footprint index, tile row y, first tile a, end tile b
+    (a >= b: empty row)."""
+    r = rect.astype(np.uint32).astype(np.int64)
+    x0, y0 = r[:, 0] & 0xFFFF, r[:, 0] >> 16
+    x1, y1 = r[:, 1] & 0xFFFF, r[:, 1] >> 16
+    h = np.maximum(y1 - y0, 0)
+    gi = np.repeat(np.arange(len(r)), h)
+    rr = np.arange(int(h.sum())) - np.repeat(np.cumsum(h) - h, h)
+    hh = h[gi]
+    m = np.where(hh > 8, hh - 4, 4)
+    top = (r[gi, 2] >> (8 * np.clip(rr, 0, 3))) & 0xFF
+    bot = (r[gi, 3] >> (8 * np.clip(rr - m, 0, 3))) & 0xFF
+    byte = np.where(rr < 4, top, np.where(rr >= m, bot, 0))
+    return gi, y0[gi] + rr, x0[gi] + (byte & 15), x1[gi] - (byte >> 4)
+
+
 def cpu_bin(depth_key: np.ndarray, rect: np.ndarray, tiles_x: int, tiles: int):
     """Reference integer stage: kept Gaussians ordered by (key, index); pairs
-    emitted row-major over each rect in that order; stable sort by tile."""
+    emitted over each footprint's tiles in that order; stable sort by tile."""
     dk = depth_key.astype(np.uint32)
     kept = np.nonzero(dk != CULLED)[0]
     order = kept[np.lexsort((kept, dk[kept]))]
-    r = rect.astype(np.uint32)
-    x0 = (r[order, 0] & 0xFFFF).astype(np.int64)
-    y0 = (r[order, 0] >> 16).astype(np.int64)
-    x1 = (r[order, 1] & 0xFFFF).astype(np.int64)
-    y1 = (r[order, 1] >> 16).astype(np.int64)
-    w = x1 - x0
-    cnt = w * (y1 - y0)
-    off = np.concatenate([[0], np.cumsum(cnt)])
-    P = int(off[-1])
-    rep = np.repeat(np.arange(len(order)), cnt)
-    loc = np.arange(P) - off[rep]
-    tile = (y0[rep] + loc // w[rep]) * tiles_x + x0[rep] + loc % w[rep]
-    g = order[rep]
+    gi, y, a, b = footprint_rows(rect[order])
+    w = np.maximum(b - a, 0)
+    P = int(w.sum())
+    rep = np.repeat(np.arange(len(w)), w)
+    loc = np.arange(P) - np.repeat(np.cumsum(w) - w, w)
+    tile = y[rep] * tiles_x + a[rep] + loc
+    g = order[gi[rep]]
     idx = np.argsort(tile, kind="stable")
     tile, g = tile[idx], g[idx]
     ranges = np.zeros((tiles, 2), np.int64)
@@ -37,6 +51,27 @@ def cpu_bin(depth_key: np.ndarray, rect: np.ndarray, tiles_x: int, tiles: int):
         ranges[tile[starts], 0] = starts
         ranges[tile[starts], 1] = ends
     return order, tile, g, ranges
+
+
+def tile_reached(sl, pr, view, g, tx, ty, chunk=4096):
+    """Per (Gaussian g, tile (tx, ty)): whether the oracle's opacity
+    alpha_c exp(-q/2) reaches 1/255 at a pixel centre of the tile inside the
+    image (FP64)."""
+    g, tx, ty = (np.asarray(x, np.int64) for x in (g, tx, ty))
+    off = np.arange(16) + 0.5
+    out = np.zeros(len(g), bool)
+    for s0 in range(0, len(g), chunk):
+        sl_ = slice(s0, s0 + chunk)
+        px = tx[sl_, None] * 16 + off[None, :]
+        py = ty[sl_, None] * 16 + off[None, :]
+        dx = (px - pr.mean2d[0][g[sl_], None])[:, None, :]
+        dy = (py - pr.mean2d[1][g[sl_], None])[:, :, None]
+        ca, cb, cc = (pr.conic[i][g[sl_], None, None] for i in range(3))
+        q = ca * dx * dx + 2 * cb * dx * dy + cc * dy * dy
+        al = sl.alpha_c[g[sl_], None, None] * np.exp(-0.5 * q)
+        inside = (px[:, None, :] < view.W) & (py[:, :, None] < view.H)
+        out[sl_] = ((al >= oracle.ALPHA_MIN) & inside).any(axis=(1, 2))
+    return out
 
 
 def slice_tolerance(ora: np.ndarray, scale: np.ndarray) -> np.ndarray:

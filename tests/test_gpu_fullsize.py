@@ -11,7 +11,7 @@ import pytest
 import oracle
 import oracle.grad as og
 import scenegen
-from tests.gpu_helpers import cpu_bin, image_check, slice_tolerance
+from tests.gpu_helpers import cpu_bin, footprint_rows, image_check, slice_tolerance
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 torch = pytest.importorskip("torch")
@@ -150,17 +150,18 @@ def test_c4_stress_scene(R, report):
     dk = b.depth_key().cpu().numpy().view(np.uint32)
     rect = b.rect().cpu().numpy().view(np.uint32)
     kept = dk != 0xFFFFFFFF
-    x0, y0 = (rect[:, 0] & 0xFFFF).astype(np.int64), (rect[:, 0] >> 16).astype(np.int64)
-    x1, y1 = (rect[:, 1] & 0xFFFF).astype(np.int64), (rect[:, 1] >> 16).astype(np.int64)
+    gi, ry, ra, rb = footprint_rows(rect)
+    live = kept[gi] & (rb > ra)
+    gi, ry, ra, rb = gi[live], ry[live], ra[live], rb[live]
     assert int(counts[0, 0]) == int(kept.sum())
-    assert int(counts[0, 1]) == int(((x1 - x0) * (y1 - y0))[kept].sum())
-    # sampled tiles: the list is every kept Gaussian whose box covers the
+    assert int(counts[0, 1]) == int((rb - ra).sum())
+    # sampled tiles: the list is every kept Gaussian whose footprint holds the
     # tile, in (depth key, index) order
     rg = b.ranges(0).cpu().numpy().astype(np.int64)
     pg = b.ws[b.layout.off_pair_g:].view(torch.int32)
     for t in np.random.default_rng(1).choice(120 * 68, 48, replace=False):
         tx, ty = t % 120, t // 120
-        cand = np.nonzero(kept & (x0 <= tx) & (tx < x1) & (y0 <= ty) & (ty < y1))[0]
+        cand = gi[(ry == ty) & (ra <= tx) & (tx < rb)]
         ref = cand[np.lexsort((cand, dk[cand]))]
         got = pg[rg[t, 0]:rg[t, 1]].cpu().numpy() if rg[t, 1] > rg[t, 0] else np.array([], np.int64)
         assert np.array_equal(got, ref), f"tile {t}"

@@ -5,7 +5,8 @@ import pytest
 
 import oracle
 import scenegen
-from tests.gpu_helpers import CULLED, cpu_bin, image_check, oracle_rect_flags, slice_tolerance
+from tests.gpu_helpers import (CULLED, cpu_bin, footprint_rows, image_check, oracle_rect_flags,
+                               slice_tolerance, tile_reached)
 
 pytestmark = pytest.mark.gpu
 
@@ -94,6 +95,37 @@ def test_project_parity(R, case):
 
 
 @pytest.mark.parametrize("case", list(CASES))
+def test_footprint_holds_every_reached_tile(R, case, report):
+    """A tile dropped from a Gaussian's tile box holds no pixel centre where the
+    oracle's opacity alpha_c exp(-q/2) reaches 1/255, so the trimmed tile lists
+    lose no contribution; and the trims do drop tiles."""
+    scene, views = CASES[case]()
+    v = views[0]
+    b = _render(R, scene, v)
+    sl = oracle.slice_(scene, v)
+    pr = oracle.project(sl, scene.sh, v)
+    flag = oracle_rect_flags(sl, pr, v)
+    dk = b.depth_key().cpu().numpy().view(np.uint32)
+    rect = b.rect().cpu().numpy().view(np.uint32)
+    use = (dk != CULLED) & pr.visible & ~flag
+    gi, ty, a, bb = footprint_rows(rect)
+    sel = use[gi]
+    gi, ty, a, bb = gi[sel], ty[sel], a[sel], bb[sel]
+    x0 = (rect[:, 0] & 0xFFFF).astype(np.int64)
+    w = (rect[:, 1] & 0xFFFF).astype(np.int64) - x0
+    wr = w[gi]
+    rep = np.repeat(np.arange(len(gi)), wr)
+    tx = x0[gi][rep] + np.arange(int(wr.sum())) - np.repeat(np.cumsum(wr) - wr, wr)
+    g, yy = gi[rep], ty[rep]
+    in_fp = (tx >= a[rep]) & (tx < bb[rep])
+    reached = tile_reached(sl, pr, v, g, tx, yy)
+    assert not np.any(reached & ~in_fp), int((reached & ~in_fp).sum())
+    dropped = int((~in_fp).sum())
+    report(f"footprint_{case}", box_tiles=len(g), dropped=dropped, unreached=int((~reached).sum()))
+    assert dropped > 0 or len(g) < 2000
+
+
+@pytest.mark.parametrize("case", list(CASES))
 def test_bin_bitexact_on_gpu_keys(R, case):
     """X15: the GPU's order, pairs and ranges equal a CPU re-execution of the
     integer stage on the GPU's own depth keys and tile boxes, bit for bit."""
@@ -120,9 +152,12 @@ def test_bin_bitexact_on_gpu_keys(R, case):
 
 @pytest.mark.parametrize("case", list(CASES))
 def test_tile_lists_match_oracle(R, case):
-    """X16: per-tile lists equal the FP64 oracle's, except Gaussians flagged as
-    within rounding of a visibility or tile-edge decision; order compared on
-    Gaussians with distinct FP32 depths."""
+    """X16: per-tile lists against the FP64 oracle's (every Gaussian whose tile
+    box covers the tile), except Gaussians flagged as within rounding of a
+    visibility or tile-edge decision: the GPU list holds every Gaussian of the
+    oracle's list that reaches alpha >= 1/255 in the tile and nothing outside
+    the oracle's list (the footprint drops only tiles a splat cannot reach);
+    order compared on Gaussians with distinct FP32 depths."""
     scene, views = CASES[case]()
     v = views[0]
     b = _render(R, scene, v)
@@ -135,10 +170,15 @@ def test_tile_lists_match_oracle(R, case):
     t_gpu, g_gpu = t_gpu.cpu().numpy(), g_gpu.cpu().numpy()
     z32 = pr.depth.astype(np.float32)
     ntiles = ((v.W + 15) // 16) * ((v.H + 15) // 16)
+    tx_ = (v.W + 15) // 16
     for t in range(ntiles):
         gl = [x for x in g_gpu[t_gpu == t] if not flag[x]]
         ol = [x for x in ora_lists.get(t, []) if not flag[x]]
-        assert sorted(gl) == sorted(ol), f"tile {t}"
+        assert set(gl) <= set(ol), f"tile {t}"
+        oa = np.array(ol, np.int64)
+        must = oa[tile_reached(sl, pr, v, oa, np.full(len(oa), t % tx_), np.full(len(oa), t // tx_))]
+        assert set(must.tolist()) <= set(gl), f"tile {t}"
+        ol = [x for x in ol if x in set(gl)]
         # order: compare after removing Gaussians that tie in FP32 depth with a neighbour
         zs = z32[np.array(ol, dtype=np.int64)] if ol else np.array([], np.float32)
         tie = np.zeros(len(ol), bool)
