@@ -26,24 +26,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# 256 CUs x 64 lanes x 2.4 GHz: one non-packed FP32 VALU operation per lane per clock
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# FP32 peak without packed math: 256 CUs x 64 lanes x one FMA (2 operations)
+# per lane per clock x 2.4 GHz.  (The published 157.3 TFLOP/s counts packed
+# FP32 FMAs, which this library is built without.)
+FP32_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 
-# Rasterizer roofline.  Unit: a wave evaluation, one (pixel, list entry) slot
-# of a tile's wave up to where the wave leaves the list (256 x entries the
-# wave traversed, summed over tiles).  Per-unit figure: the VALU lane
-# operations the kernel issues per evaluation, from the SQ_INSTS_VALU counter
-# (x 64 lanes) over one launch of this workload divided by its evaluations;
-# by the instruction listing of the kernel it is 5 per evaluation for the
-# exponent and the opacity test plus 11 per pixel slot of every band whose
-# blend runs.  Traffic: FETCH_SIZE x 2 + WRITE_SIZE (KiB x 1024) per launch,
-# scaling factors from a 1 GiB device copy.  Both were taken for the kernel
-# source whose digest is RASTER_SRC_SHA256 and are dropped (traffic null,
-# counters_current false) once the source differs.
+# Rasterizer roofline, in algorithmic FP32 operations of the compositing as the
+# method defines it.  Per (pixel, splat) test -- every list entry a pixel
+# consumes -- 12: the offsets (2), the exponent A dx^2 + B dx dy + C dy^2 + lo
+# (3 squares/products, 3 coefficient products, 3 adds) and the opacity
+# threshold test (1).  Per contribution -- a test that passes and does not stop
+# the pixel -- 12 more: 2^p and the 0.99 clamp (2), T' = T (1 - alpha) (2),
+# the stop test (1), w = T alpha (1) and three colour FMAs (6).  Traffic:
+# FETCH_SIZE x 2 + WRITE_SIZE (KiB x 1024) per launch, scaling factors from a
+# 1 GiB device copy, taken for the kernel source whose digest is
+# RASTER_SRC_SHA256 (null once the source differs), with the VALU instruction
+# count of the same runs.
+RASTER_OPS_PER_TEST = 12
+RASTER_OPS_PER_CONTRIBUTION = 12
 RASTER_SRC = ("paper_2503_07946_amd/csrc/raster.hip", "paper_2503_07946_amd/csrc/common.h")
-RASTER_SRC_SHA256 = "c42410d329e9ee4a71e3a3aadb84424c0d8fa2d750651982904a1dbcee8860cf"
-RASTER_VALU_OPS_PER_EVAL = 10.83        # 1.478e9 VALU instructions x 64 / 8.733e9 evaluations
-RASTER_TRAFFIC_BYTES = 2795034624       # (1208513 KiB x 2 + 312500 KiB) x 1024
+RASTER_SRC_SHA256 = "e6304134324d84557c56238ab3fa71cc23ff7871154cf073cbd9961770f9e862"
+RASTER_TRAFFIC_BYTES = 2420979920       # (1025869 KiB x 2 + 312500 KiB) x 1024
+RASTER_VALU_INSTRUCTIONS = 1133839814   # SQ_INSTS_VALU per launch (wave64 instructions)
 
 
 def raster_src_digest() -> str:
@@ -286,16 +290,20 @@ def main():
     t_r = stage_avg["sd7_rasterize"] * 1e-3                        # per batch launch, s
     evals_l = evals / len(batches)
     current = RASTER_SRC_SHA256 is not None and raster_src_digest() == RASTER_SRC_SHA256
-    per_eval = RASTER_VALU_OPS_PER_EVAL
-    achieved = evals_l * per_eval / t_r / 1e12
+    tests_l, contribs_l = tests / len(batches), contribs / len(batches)
+    flops_l = RASTER_OPS_PER_TEST * tests_l + RASTER_OPS_PER_CONTRIBUTION * contribs_l
+    achieved = flops_l / t_r / 1e12
     roofline = {"bound": "alu", "kernel": "k_raster", "achieved": round(achieved, 3),
-                "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                "peak": round(FP32_PEAK_TFLOPS, 2), "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                 "traffic": RASTER_TRAFFIC_BYTES if current else None,
-                "algorithmic_units": {"wave_evaluations_per_launch": int(evals_l),
-                                      "valu_lane_ops_per_evaluation": per_eval,
-                                      "pixel_tests_per_launch": int(tests / len(batches)),
-                                      "contributions_per_launch": int(contribs / len(batches))},
+                "algorithmic_units": {"pixel_tests_per_launch": int(tests_l),
+                                      "contributions_per_launch": int(contribs_l),
+                                      "ops_per_test": RASTER_OPS_PER_TEST,
+                                      "ops_per_contribution": RASTER_OPS_PER_CONTRIBUTION,
+                                      "fp32_ops_per_launch": int(flops_l),
+                                      "wave_evaluations_per_launch": int(evals_l)},
                 "counters_current": current,
+                "valu_instructions_per_launch": RASTER_VALU_INSTRUCTIONS if current else None,
                 "avg_launch_ms": round(stage_avg["sd7_rasterize"], 4)}
 
     # -- latency: batched (frames of a batch finish with their batch) vs plain
