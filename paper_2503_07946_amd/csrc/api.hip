@@ -360,17 +360,25 @@ sd7_status fill(const Call& c, void* p, size_t count, uint32_t value)
 }
 
 // Exclusive scan in place; the length is host-known (len_dev null) or read on
-// the device.  The grand total lands in partials[ntiles] and *total_out.
+// the device; the grand total goes to *total_out when asked for.  Up to
+// kScanCarryTiles work tiles (by max_len) the down-sweep adds up the tile
+// sums itself; longer scans take a spine pass between.
 // part: at least max_len / kScanItems + 4 entries.
 sd7_status scan_with(hipStream_t st, uint32_t* part, uint32_t* data, uint32_t len_host, const uint32_t* len_dev,
                      uint32_t max_len, uint32_t* total_out)
 {
-    const uint32_t blocks = std::max(1u, std::min<uint32_t>(ceil_div(max_len, kScanItems), kPersistentBlocks));
+    const uint32_t tiles = ceil_div(max_len, kScanItems);
+    const uint32_t blocks = std::max(1u, std::min<uint32_t>(tiles, kPersistentBlocks));
     k_scan_reduce<<<blocks, 256, 0, st>>>(data, len_host, len_dev, part);
     LAUNCH_CHECK("k_scan_reduce");
+    if (tiles <= kScanCarryTiles) {
+        k_scan_down<true><<<blocks, 256, 0, st>>>(data, data, len_host, len_dev, part, total_out);
+        LAUNCH_CHECK("k_scan_down");
+        return SD7_OK;
+    }
     k_scan_spine<<<1, 1024, 0, st>>>(part, len_host, len_dev, total_out);
     LAUNCH_CHECK("k_scan_spine");
-    k_scan_down<<<blocks, 256, 0, st>>>(data, data, len_host, len_dev, part);
+    k_scan_down<false><<<blocks, 256, 0, st>>>(data, data, len_host, len_dev, part, nullptr);
     LAUNCH_CHECK("k_scan_down");
     return SD7_OK;
 }

@@ -116,14 +116,34 @@ __global__ __launch_bounds__(1024) void k_scan_spine(uint32_t* __restrict__ part
     }
 }
 
+// Down-sweep: each work tile's exclusive scan plus the tile's carry.  SUMS:
+// the partials are the raw tile sums and each tile adds up those before it
+// itself (no spine pass; for scans of at most kScanCarryTiles tiles), and the
+// last tile writes the grand total to *total_out; otherwise the partials hold
+// the spine's exclusive carries.
+constexpr uint32_t kScanCarryTiles = 2048;
+
+template <bool SUMS>
 __global__ __launch_bounds__(256) void k_scan_down(const uint32_t* in, uint32_t* out, uint32_t len_host,
                                                    const uint32_t* __restrict__ len_dev,
-                                                   const uint32_t* __restrict__ partials)
+                                                   const uint32_t* __restrict__ partials,
+                                                   uint32_t* __restrict__ total_out)
 {
     __shared__ uint32_t s_tmp[4];
     const uint32_t len = len_dev ? *len_dev : len_host;
     const uint32_t ntiles = (len + kScanItems - 1) / kScanItems;
+    if (SUMS && ntiles == 0 && total_out && blockIdx.x == 0 && threadIdx.x == 0) *total_out = 0;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        uint32_t carry;
+        if (SUMS) {
+            uint32_t c = 0;
+            for (uint32_t i = threadIdx.x; i < t; i += 256) c += partials[i];
+            uint32_t ctot;
+            block_excl_scan(c, s_tmp, ctot);
+            carry = ctot;
+        } else {
+            carry = partials[t];
+        }
         const uint32_t base = t * kScanItems + threadIdx.x * 16;
         uint32_t v[16];
         const bool full = base + 16 <= len;
@@ -142,7 +162,8 @@ __global__ __launch_bounds__(256) void k_scan_down(const uint32_t* in, uint32_t*
 #pragma unroll
         for (int k = 0; k < 16; ++k) s += v[k];
         uint32_t total;
-        uint32_t run = block_excl_scan(s, s_tmp, total) + partials[t];
+        uint32_t run = block_excl_scan(s, s_tmp, total) + carry;
+        if (SUMS && t + 1 == ntiles && total_out && threadIdx.x == 0) *total_out = carry + total;
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             const uint32_t x = v[k];
@@ -280,29 +301,43 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, size_t count, uint32_t valu
 }
 
 // Segments of the depth sort.  segs_all: every Gaussian (the compacting first
-// pass); segs_kept: the kept ones.
-__global__ void k_setup_depth(const FrameDev* __restrict__ tab, int nf, const uint32_t* __restrict__ counts,
-                              SortSeg* __restrict__ segs_all, SortTotals* __restrict__ tot_all,
-                              SortSeg* __restrict__ segs_kept, SortTotals* __restrict__ tot_kept)
+// pass); segs_kept: the kept ones.  One wave, lane f = frame f (at most 64
+// frames); offsets are wave prefix sums.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t lane)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    uint32_t wt_all = 0, wt_kept = 0, excl = 0;
-    for (int f = 0; f < nf; ++f) {
-        const uint32_t n = tab[f].n, g0 = tab[f].g0;
-        const uint32_t kept = counts[f * SD7_CNT_WORDS + SD7_CNT_KEPT];
-        SortSeg a;
-        a.in_base = g0; a.out_base = g0; a.len = n; a.wt0 = wt_all;
-        a.nwt = (n + kSortItems - 1) / kSortItems; a.cnt_excl = excl; a.pad[0] = a.pad[1] = 0;
-        SortSeg b = a;
-        b.len = kept; b.wt0 = wt_kept; b.nwt = (kept + kSortItems - 1) / kSortItems;
-        segs_all[f] = a;
-        segs_kept[f] = b;
-        wt_all += a.nwt;
-        wt_kept += b.nwt;
-        excl += kept;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_up(v, off);
+        if (lane >= (uint32_t)off) v += t;
     }
-    tot_all->wt = wt_all; tot_all->hist_len = 256u * wt_all;
-    tot_kept->wt = wt_kept; tot_kept->hist_len = 256u * wt_kept;
+    return v;
+}
+
+__global__ __launch_bounds__(64) void k_setup_depth(const FrameDev* __restrict__ tab, int nf,
+                                                    const uint32_t* __restrict__ counts,
+                                                    SortSeg* __restrict__ segs_all, SortTotals* __restrict__ tot_all,
+                                                    SortSeg* __restrict__ segs_kept, SortTotals* __restrict__ tot_kept)
+{
+    const uint32_t lane = threadIdx.x;
+    const bool live = (int)lane < nf;
+    const uint32_t n = live ? tab[lane].n : 0u, g0 = live ? tab[lane].g0 : 0u;
+    const uint32_t kept = live ? counts[lane * SD7_CNT_WORDS + SD7_CNT_KEPT] : 0u;
+    const uint32_t nwa = (n + kSortItems - 1) / kSortItems, nwk = (kept + kSortItems - 1) / kSortItems;
+    const uint32_t wa = wave_incl_scan(nwa, lane), wk = wave_incl_scan(nwk, lane);
+    const uint32_t ex = wave_incl_scan(kept, lane);
+    if (live) {
+        SortSeg a;
+        a.in_base = g0; a.out_base = g0; a.len = n; a.wt0 = wa - nwa;
+        a.nwt = nwa; a.cnt_excl = ex - kept; a.pad[0] = a.pad[1] = 0;
+        SortSeg b = a;
+        b.len = kept; b.wt0 = wk - nwk; b.nwt = nwk;
+        segs_all[lane] = a;
+        segs_kept[lane] = b;
+    }
+    if (lane == 63) {
+        tot_all->wt = wa; tot_all->hist_len = 256u * wa;
+        tot_kept->wt = wk; tot_kept->hist_len = 256u * wk;
+    }
 }
 
 // Tiles of each Gaussian's footprint in depth order (0 past the kept ones)
@@ -331,43 +366,59 @@ __global__ __launch_bounds__(kBlock) void k_gather_ntiles(const FrameDev* __rest
 }
 
 // Per-frame pair counts, arena slots (each frame's share rounded up to a whole
-// number of sort work tiles) and the tile-sort segments.
-__global__ void k_setup_pairs(const FrameDev* __restrict__ tab, int nf, uint32_t n_total,
-                              const uint32_t* __restrict__ toff, const uint32_t* __restrict__ toff_total,
-                              uint32_t capacity, uint32_t* __restrict__ counts,
-                              SortSeg* __restrict__ segs, SortTotals* __restrict__ tot)
+// number of sort work tiles) and the tile-sort segments.  One wave, lane f =
+// frame f: the frames' pair counts are read in parallel; the arena is then
+// handed out in frame order (a frame that does not fit gets none, and later
+// frames may still fit), a walk over values already in registers.
+__global__ __launch_bounds__(64) void k_setup_pairs(const FrameDev* __restrict__ tab, int nf, uint32_t n_total,
+                                                    const uint32_t* __restrict__ toff,
+                                                    const uint32_t* __restrict__ toff_total, uint32_t capacity,
+                                                    uint32_t* __restrict__ counts, SortSeg* __restrict__ segs,
+                                                    SortTotals* __restrict__ tot)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const uint32_t lane = threadIdx.x;
+    const bool live = (int)lane < nf;
     const uint32_t total = *toff_total;
-    uint32_t base = 0, wt = 0, excl = 0;
-    for (int f = 0; f < nf; ++f) {
-        const uint32_t g0 = tab[f].g0, n = tab[f].n;
-        const uint32_t lo = g0 < n_total ? toff[g0] : total;
+    uint32_t P = 0, lo = 0;
+    if (live) {
+        const uint32_t g0 = tab[lane].g0, n = tab[lane].n;
+        lo = g0 < n_total ? toff[g0] : total;
         const uint32_t hi = (g0 + n) < n_total ? toff[g0 + n] : total;
-        uint32_t P = hi - lo;
-        uint32_t* c = counts + f * SD7_CNT_WORDS;
-        c[SD7_CNT_FLAGS] &= ~SD7_FLAG_PAIR_OVERFLOW;  // binning may be re-run with a larger arena
-        if ((uint64_t)base + P > capacity) {
-            c[SD7_CNT_FLAGS] |= SD7_FLAG_PAIR_OVERFLOW;
-            c[SD7_CNT_PAIRS] = 0;
-            c[4] = P;  // pairs the frame needed
-            P = 0;
-        } else {
-            c[SD7_CNT_PAIRS] = P;
-            c[4] = P;
-        }
-        c[SD7_CNT_PAIR_BASE] = base;
-        c[5] = lo;  // scan value at the frame's first Gaussian
-        SortSeg s;
-        s.in_base = base; s.out_base = base; s.len = P; s.wt0 = wt;
-        s.nwt = (P + kSortItems - 1) / kSortItems; s.cnt_excl = excl; s.pad[0] = s.pad[1] = 0;
-        segs[f] = s;
-        wt += s.nwt;
-        excl += P;
-        base += s.nwt * kSortItems;
+        P = hi - lo;
     }
-    tot->wt = wt;
-    tot->hist_len = 256u * wt;
+    uint32_t base = 0, wt = 0, excl = 0;
+    uint32_t my_base = 0, my_wt = 0, my_excl = 0, my_len = 0;
+    bool my_ov = false;
+    for (int f = 0; f < nf; ++f) {
+        const uint32_t Pf = __builtin_amdgcn_readlane(P, f);
+        const bool ov = (uint64_t)base + Pf > capacity;
+        const uint32_t len = ov ? 0u : Pf;
+        const uint32_t nwt = (len + kSortItems - 1) / kSortItems;
+        if (lane == (uint32_t)f) {
+            my_base = base; my_wt = wt; my_excl = excl; my_len = len; my_ov = ov;
+        }
+        wt += nwt;
+        excl += len;
+        base += nwt * kSortItems;
+    }
+    if (live) {
+        uint32_t* c = counts + lane * SD7_CNT_WORDS;
+        // binning may be re-run with a larger arena: the flag is recomputed
+        const uint32_t fl = c[SD7_CNT_FLAGS] & ~SD7_FLAG_PAIR_OVERFLOW;
+        c[SD7_CNT_FLAGS] = my_ov ? (fl | SD7_FLAG_PAIR_OVERFLOW) : fl;
+        c[SD7_CNT_PAIRS] = my_len;
+        c[4] = P;  // pairs the frame needs
+        c[SD7_CNT_PAIR_BASE] = my_base;
+        c[5] = lo;  // scan value at the frame's first Gaussian
+        SortSeg sg;
+        sg.in_base = my_base; sg.out_base = my_base; sg.len = my_len; sg.wt0 = my_wt;
+        sg.nwt = (my_len + kSortItems - 1) / kSortItems; sg.cnt_excl = my_excl; sg.pad[0] = sg.pad[1] = 0;
+        segs[lane] = sg;
+    }
+    if (lane == 0) {
+        tot->wt = wt;
+        tot->hist_len = 256u * wt;
+    }
 }
 
 // Tile id of the l-th tile of a footprint (row by row, left to right);
