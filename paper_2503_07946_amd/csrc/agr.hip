@@ -10,6 +10,7 @@
 // C_out per hidden unit for the second layer, 4032 FP32 multiply-adds in
 // all, with the weights read from LDS as broadcasts.
 #include "common.h"
+#include "gload.h"
 
 namespace sd7 {
 
@@ -54,7 +55,7 @@ __device__ __forceinline__ void mlp_layer2(const float* __restrict__ s_hid, cons
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_agr_slice(const FrameDev* __restrict__ tab, BlockMap bm,
+__global__ __launch_bounds__(kBlock, 4) void k_agr_slice(const FrameDev* __restrict__ tab, BlockMap bm,
                                                       float* __restrict__ mu_c, float* __restrict__ cov_c,
                                                       float* __restrict__ alpha_c, uint32_t* __restrict__ counts)
 {
@@ -74,23 +75,31 @@ __global__ __launch_bounds__(kBlock) void k_agr_slice(const FrameDev* __restrict
     if (tid < 35) {
         const int m = tid < 3 ? 0 : tid < 4 ? 1 : tid < 7 ? 2 : 3;
         const int o = tid - (m == 0 ? 0 : m == 1 ? 3 : m == 2 ? 4 : 7);
-        s_b2[tid] = W[agr_base(m) + kAgrHidden * kAgrIn + kAgrHidden + kAgrOut[m] * kAgrHidden + o];
+        s_b2[tid] = gload(W, agr_base(m) + kAgrHidden * kAgrIn + kAgrHidden + kAgrOut[m] * kAgrHidden + o);
     }
     __syncthreads();
     {
+        // every weight the thread stages is loaded before its first LDS store
         const int m = tid / kAgrHidden, j = tid % kAgrHidden;  // 256 threads = 4 MLPs x 64 units
         const float* W1 = W + agr_base(m) + j * kAgrIn;
-        const float b1 = W[agr_base(m) + kAgrHidden * kAgrIn + j];
+        const float* W2 = W + agr_base(m) + kAgrHidden * kAgrIn + kAgrHidden;
+        float w1[kAgrIn], w2[28];
+#pragma unroll
+        for (int c = 0; c < kAgrIn; ++c) w1[c] = gload(W1, c);
+        const float b1 = gload(W, agr_base(m) + kAgrHidden * kAgrIn + j);
+#pragma unroll
+        for (int o = 0; o < 28; ++o) w2[o] = o < kAgrOut[m] ? gload(W2, o * kAgrHidden + j) : 0.0f;
         double bias = (double)b1;
 #pragma unroll
-        for (int k = 0; k < 2 * kAgrK; ++k) bias = fma((double)W1[7 + k], s_gam[k], bias);
+        for (int k = 0; k < 2 * kAgrK; ++k) bias = fma((double)w1[7 + k], s_gam[k], bias);
         float* hrow = s_hid + (m * kAgrHidden + j) * 8;
 #pragma unroll
-        for (int c = 0; c < 7; ++c) hrow[c] = W1[c];
+        for (int c = 0; c < 7; ++c) hrow[c] = w1[c];
         hrow[7] = (float)bias;
-        const float* W2 = W + agr_base(m) + kAgrHidden * kAgrIn + kAgrHidden;
         float* w2row = s_w2 + kW2Off[m] + j * kW2Stride[m];
-        for (int o = 0; o < kAgrOut[m]; ++o) w2row[o] = W2[o * kAgrHidden + j];
+#pragma unroll
+        for (int o = 0; o < 28; ++o)
+            if (o < kAgrOut[m]) w2row[o] = w2[o];
     }
     __syncthreads();
 
@@ -100,10 +109,10 @@ __global__ __launch_bounds__(kBlock) void k_agr_slice(const FrameDev* __restrict
         const uint32_t n = F.n;
         float x[7];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) x[a] = F.mu_p[(size_t)a * n + i];
-        x[3] = F.mu_t[i];
+        for (int a = 0; a < 3; ++a) x[a] = gload(F.mu_p, (size_t)a * n + i);
+        x[3] = gload(F.mu_t, i);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) x[4 + a] = F.mu_d[(size_t)a * n + i];
+        for (int a = 0; a < 3; ++a) x[4 + a] = gload(F.mu_d, (size_t)a * n + i);
         float rp[3], rt[1], rd[3], rl[28];
 #pragma unroll
         for (int o = 0; o < 3; ++o) rp[o] = s_b2[o];
@@ -119,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void k_agr_slice(const FrameDev* __restrict
         // refined parameters (FP32), then the slice of k_slice
         double L[28];
 #pragma unroll
-        for (int k = 0; k < 28; ++k) L[k] = (double)(F.L[(size_t)k * n + i] + rl[k]);
+        for (int k = 0; k < 28; ++k) L[k] = (double)(gload(F.L, (size_t)k * n + i) + rl[k]);
         SliceFixed S;
         slice_fixed(L, S, flag);
         float cv32[6];
@@ -135,7 +144,7 @@ __global__ __launch_bounds__(kBlock) void k_agr_slice(const FrameDev* __restrict
         view_direction(F, mu_p, d, rn);
         slice_view<false>(S, (double)F.t, d, rn, (double)(x[3] + rt[0]), mu_d, F.lambda_t, F.lambda_d, V);
         float mc[3], cv[6], ac;
-        slice_outputs(S, V, mu_p, cv32, cv_fin, F.alpha[i], mc, cv, ac, flag);
+        slice_outputs(S, V, mu_p, cv32, cv_fin, gload(F.alpha, i), mc, cv, ac, flag);
         const size_t g0 = F.g0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) mu_c[3 * g0 + (size_t)a * n + i] = mc[a];

@@ -17,6 +17,7 @@
 // Sizes that depend on the data (kept Gaussians, pairs) stay on the device;
 // the kernels that need them run persistent grids over work tiles.
 #include "common.h"
+#include "footprint.h"
 
 namespace sd7 {
 

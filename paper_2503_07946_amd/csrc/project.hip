@@ -8,6 +8,8 @@
 // gets a (tile, Gaussian) pair, so tiles list every Gaussian that can reach
 // alpha >= 1/255 at one of their pixel centres.
 #include "common.h"
+#include "footprint.h"
+#include "gload.h"
 
 namespace sd7 {
 
@@ -169,7 +171,7 @@ __device__ __forceinline__ uint2 footprint_trims(const Proj& p, float k, uint32_
 struct ShGlobal {
     const float* __restrict__ sh;
     uint32_t n;
-    __device__ __forceinline__ float operator()(int j, uint32_t i) const { return sh[(size_t)j * n + i]; }
+    __device__ __forceinline__ float operator()(int j, uint32_t i) const { return gload(sh, (size_t)j * n + i); }
 };
 
 // Projection, footprint, colour and the splat record of Gaussian i of frame F
@@ -309,7 +311,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(const FrameDev* __restri
             float s = 0.5f;
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
-                b[k] = F.sh[(size_t)(3 * k + ch) * n + i];
+                b[k] = gload(F.sh, (size_t)(3 * k + ch) * n + i);
                 s += b[k] * Y[k];
             }
             const float graw = s > 0.0f ? ds[6 + ch] : 0.0f;

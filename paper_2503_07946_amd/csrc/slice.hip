@@ -11,6 +11,7 @@
 // Loads are coalesced: each of the 36 input planes is read with consecutive
 // lanes on consecutive Gaussians.
 #include "common.h"
+#include "gload.h"
 
 namespace sd7 {
 
@@ -57,7 +58,7 @@ struct SliceState : SliceFixed, SliceView {
 __device__ __forceinline__ void load_L(const float* __restrict__ Lp, uint32_t n, uint32_t i, double L[28])
 {
 #pragma unroll
-    for (int k = 0; k < 28; ++k) L[k] = (double)Lp[(size_t)k * n + i];
+    for (int k = 0; k < 28; ++k) L[k] = (double)gload(Lp, (size_t)k * n + i);
 }
 
 __device__ __forceinline__ void slice_fixed(const double L[28], SliceFixed& S, uint32_t& flag)
@@ -206,14 +207,14 @@ __device__ __forceinline__ void slice_state(const FrameDev& F, uint32_t i, Slice
     slice_fixed(S.L, S, flag);
     double mu_d[3], d[3], rn;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) mu_d[k] = (double)F.mu_d[(size_t)k * n + i];
+    for (int k = 0; k < 3; ++k) mu_d[k] = (double)gload(F.mu_d, (size_t)k * n + i);
     float mu_p[3] = {0.f, 0.f, 0.f};
     if (F.d_mode) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) mu_p[k] = F.mu_p[(size_t)k * n + i];
+        for (int k = 0; k < 3; ++k) mu_p[k] = gload(F.mu_p, (size_t)k * n + i);
     }
     view_direction(F, mu_p, d, rn);
-    slice_view<WITH_Y>(S, (double)F.t, d, rn, (double)F.mu_t[i], mu_d, F.lambda_t, F.lambda_d, S);
+    slice_view<WITH_Y>(S, (double)F.t, d, rn, (double)gload(F.mu_t, i), mu_d, F.lambda_t, F.lambda_d, S);
 }
 
 // Sigma_c = Sigma_PP - V V^T (eq. cond_cov), packed (xx, xy, xz, yy, yz, zz),
@@ -286,10 +287,10 @@ __global__ __launch_bounds__(kBlock) void k_slice(const FrameDev* __restrict__ t
         slice_state<false>(F, i, S, flag);
         float mu_p[3], cv32[6];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) mu_p[a] = F.mu_p[(size_t)a * n + i];
+        for (int a = 0; a < 3; ++a) mu_p[a] = gload(F.mu_p, (size_t)a * n + i);
         const bool cv_fin = slice_cov(S, cv32);
         float mc[3], cv[6], ac;
-        slice_outputs(S, S, mu_p, cv32, cv_fin, F.alpha[i], mc, cv, ac, flag);
+        slice_outputs(S, S, mu_p, cv32, cv_fin, gload(F.alpha, i), mc, cv, ac, flag);
         const size_t g0 = F.g0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) mu_c[3 * g0 + (size_t)a * n + i] = mc[a];
@@ -400,7 +401,7 @@ __global__ __launch_bounds__(kBlock) void k_slice_bwd(const FrameDev* __restrict
         for (int k = 0; k < 3; ++k) out_mu_d[k] = -Kg[1 + k];
         // modulation: alpha_c = alpha exp(-(e_t + e_d)/2)
         const double fmod = exp(-0.5 * (S.e_t + S.e_d));
-        const double alpha = (double)F.alpha[i];
+        const double alpha = (double)gload(F.alpha, i);
         out_alpha = ga * fmod;
         const double s = ga * alpha * fmod;  // dl/d(ln alpha_c)
         const double lt = (double)F.lambda_t, ld = (double)F.lambda_d;

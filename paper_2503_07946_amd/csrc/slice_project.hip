@@ -14,6 +14,7 @@
 // k_slice and k_project, so every output is bitwise the same as the two
 // separate kernels'.
 #include "common.h"
+#include "gload.h"
 
 namespace sd7 {
 
@@ -46,21 +47,23 @@ __global__ __launch_bounds__(kBlock, 3) void k_slice_project(const FrameDev* __r
     uint32_t flag0 = 0;
     __shared__ float s_sh[48 * kBlock];
     if (valid) {
-#pragma unroll 8
-        for (int j = 0; j < 48; ++j) s_sh[j * kBlock + threadIdx.x] = F0.sh[(size_t)j * n + i];
-    }
-    // each lane reads back only what it wrote: no barrier needed
-    if (valid) {
+        // every load of the Gaussian is issued before the first LDS store
+        float sh[48];
+#pragma unroll
+        for (int j = 0; j < 48; ++j) sh[j] = gload(F0.sh, (size_t)j * n + i);
         double L[28];
         load_L(F0.L, n, i, L);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) mu_p[a] = gload(F0.mu_p, (size_t)a * n + i);
+        mu_t = gload(F0.mu_t, i);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) mu_d[k] = gload(F0.mu_d, (size_t)k * n + i);
+        alpha = gload(F0.alpha, i);
+#pragma unroll
+        for (int j = 0; j < 48; ++j) s_sh[j * kBlock + threadIdx.x] = sh[j];
+        // each lane reads back only what it wrote: no barrier needed
         slice_fixed(L, S, flag0);
         cv_fin = slice_cov(S, cv32);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) mu_p[a] = F0.mu_p[(size_t)a * n + i];
-        mu_t = F0.mu_t[i];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) mu_d[k] = F0.mu_d[(size_t)k * n + i];
-        alpha = F0.alpha[i];
     }
     // the group's frames split into nchunk runs of nearly equal length
     const uint32_t q0 = sg.first[gi] + chunk * nq / nchunk;
