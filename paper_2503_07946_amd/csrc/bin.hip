@@ -656,39 +656,16 @@ __global__ __launch_bounds__(64) void k_group_place(const FrameDev* __restrict__
     }
     const uint4* rf = srect + F.g0;
     const uint32_t* of = order + F.g0;
-    // the boxes and indices of the next kBinAhead x 64 Gaussians are loaded
-    // while the current ones are visited; empty boxes past j1
-    uint4 rn[kBinAhead];
-    uint32_t gn[kBinAhead];
-#pragma unroll
-    for (int k = 0; k < kBinAhead; ++k) {
-        const uint32_t jj = j0 + k * 64 + lane;
-        rn[k] = make_uint4(0u, 0u, 0u, 0u);
-        gn[k] = 0;
-        if (jj < j1) {
-            rn[k] = rf[jj];
-            gn[k] = of[jj];
-        }
-    }
-    for (uint32_t j = j0; j < j1; j += kBinAhead * 64) {
-        uint4 r[kBinAhead];
-        uint32_t g[kBinAhead];
-#pragma unroll
-        for (int k = 0; k < kBinAhead; ++k) {
-            r[k] = rn[k];
-            g[k] = gn[k];
-            const uint32_t jj = j + (kBinAhead + k) * 64 + lane;
-            rn[k] = make_uint4(0u, 0u, 0u, 0u);
-            if (jj < j1) {
-                rn[k] = rf[jj];
-                gn[k] = of[jj];
-            }
-        }
+    // Visit the footprints of entries jb + k * 64 + lane (k < kBinAhead) that
+    // meet the group, in depth order; entries past j1 (loaded in bounds from
+    // j1 - 1) take no part.
+    auto visit = [&](const uint4 (&r)[kBinAhead], const uint32_t (&g)[kBinAhead], uint32_t jb) {
 #pragma unroll
         for (int k = 0; k < kBinAhead; ++k) {
             const uint32_t x0 = r[k].x & 0xFFFFu, y0 = r[k].x >> 16;
             const uint32_t x1 = r[k].y & 0xFFFFu, y1 = r[k].y >> 16;
-            const bool meets = x0 < bx0 + kGroup && x1 > bx0 && y0 < by0 + kGroup && y1 > by0;
+            const bool meets = (jb + k * 64 + lane < j1) & (x0 < bx0 + kGroup) & (x1 > bx0) &
+                               (y0 < by0 + kGroup) & (y1 > by0);
             uint64_t m = __ballot(meets);
             while (m) {  // the meeting boxes in depth order
                 const int p = __builtin_ctzll(m);
@@ -705,6 +682,27 @@ __global__ __launch_bounds__(64) void k_group_place(const FrameDev* __restrict__
                 if (hit) pair_g[slot++] = gp;
             }
         }
+    };
+    auto load = [&](uint4 (&r)[kBinAhead], uint32_t (&g)[kBinAhead], uint32_t jb) {
+#pragma unroll
+        for (int k = 0; k < kBinAhead; ++k) {
+            const uint32_t jj = min(jb + k * 64 + lane, j1 - 1);
+            r[k] = rf[jj];
+            g[k] = of[jj];
+        }
+    };
+    // Two sets of footprints in flight: one is visited while the next one
+    // loads, alternating without register copies.
+    uint4 ra[kBinAhead], rb[kBinAhead];
+    uint32_t ga[kBinAhead], gb[kBinAhead];
+    load(ra, ga, j0);
+    for (uint32_t j = j0; j < j1; j += 2 * kBinAhead * 64) {
+        const uint32_t jn = j + kBinAhead * 64;
+        load(rb, gb, jn);
+        visit(ra, ga, j);
+        if (jn >= j1) break;
+        load(ra, ga, jn + kBinAhead * 64);
+        visit(rb, gb, jn);
     }
 }
 
