@@ -80,6 +80,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--views", type=int, default=50)
     ap.add_argument("--batch", type=int, default=25, help="frames per set of launches")
+    ap.add_argument("--streams", type=int, default=2, help="HIP streams the batches of a step alternate over")
     ap.add_argument("--gaussians", type=int, default=200_000)
     ap.add_argument("--plain-frames", type=int, default=20, help="frames timed one per call")
     ap.add_argument("--cpu-baseline", type=int, default=1)
@@ -150,7 +151,59 @@ def serve_bench(a, R, L):
             "plain": sp, "batched": sb}
 
 
-def agr_bench(a, R, L, scene, views):
+def run_steps(R, batches, steps, streams, record_stage=None):
+    """`steps` passes over the batches, batch i on streams[i % len(streams)]
+    (a batch's stages stay ordered on its stream; the batches of a step are
+    independent, so one batch's slicing and binning overlap another's
+    compositing).  With record_stage, HIP events on the batch's stream bracket
+    that stage of every batch; returns (seconds, [ms per launch])."""
+    import torch
+    names = ("sd7_slice_project", "sd7_bin", "sd7_rasterize")
+    ev = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for i, b in enumerate(batches):
+            st = streams[i % len(streams)]
+            if record_stage is None:
+                R.stage("sd7_render", b, stream=st)
+                continue
+            for s in names:
+                if s == record_stage:
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(st)
+                    R.stage(s, b, stream=st)
+                    e1.record(st)
+                    ev.append((e0, e1))
+                else:
+                    R.stage(s, b, stream=st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt, [e0.elapsed_time(e1) for e0, e1 in ev]
+
+
+def serial_stage_ms(R, batches, reps):
+    """Per-step milliseconds of each stage, one stream, no overlap."""
+    import numpy as np
+    import torch
+    names = ("sd7_slice_project", "sd7_bin", "sd7_rasterize")
+    stream = torch.cuda.current_stream()
+    ms = {s: [] for s in names}
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        for b in batches:
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+            e[0].record(stream)
+            for k, s in enumerate(names):
+                R.stage(s, b, stream=stream)
+                e[k + 1].record(stream)
+            torch.cuda.synchronize()
+            for k, s in enumerate(names):
+                ms[s].append(e[k].elapsed_time(e[k + 1]))
+    return {s: round(float(np.mean(v)) * len(batches), 4) for s, v in ms.items()}
+
+
+def agr_bench(a, R, L, scene, views, streams):
     """The full 7DGS variant: the same scenes and views with adaptive Gaussian
     refinement (Sec. 4.3) before the slice, weights from scenegen.agr_weights(1)."""
     import numpy as np
@@ -167,30 +220,12 @@ def agr_bench(a, R, L, scene, views):
         c = R.read_counts(R.render_frames(frames, exact=True))
         need = int(sum((int(p) + 4095) // 4096 * 4096 for p in c[:, L.SD7_CNT_NEEDED]))
         batches.append(R.batch(frames, int(need * 1.05) + 4096))
-    stream = torch.cuda.current_stream()
-    stages = ("sd7_slice_project", "sd7_bin", "sd7_rasterize")
-    for _ in range(a.warmup):
-        for b in batches:
-            R.stage("sd7_render", b)
-    torch.cuda.synchronize()
-    ev = []
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        for b in batches:
-            e = [torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
-            e[0].record(stream)
-            for k, st in enumerate(stages):
-                R.stage(st, b)
-                e[k + 1].record(stream)
-            ev.append(e)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    run_steps(R, batches, a.warmup, streams)
+    dt, _ = run_steps(R, batches, a.steps, streams)
     over = sum(int(np.sum(R.read_counts(b)[:, L.SD7_CNT_FLAGS] & L.SD7_FLAG_PAIR_OVERFLOW != 0)) for b in batches)
-    per = {st: float(np.mean([e[k].elapsed_time(e[k + 1]) for e in ev])) * len(batches)
-           for k, st in enumerate(stages)}
     return {"value": round(len(views) * a.steps / dt, 2), "unit": "FPS",
             "ms_per_step": round(1e3 * dt / a.steps, 3),
-            "stage_ms_per_step": {k: round(v, 4) for k, v in per.items()},
+            "stage_ms_per_step": serial_stage_ms(R, batches, 2),
             "overflowed_frames": over, "weights": "scenegen.agr_weights(1)"}
 
 
@@ -235,30 +270,10 @@ def main():
         batches.append(R.batch(frames, cap))
     torch.cuda.synchronize()
 
-    stages = ("sd7_slice_project", "sd7_bin", "sd7_rasterize")
-    ev = []
-
-    def step(record=False):
-        for b in batches:
-            if record:
-                e = [torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
-                e[0].record(stream)
-                for k, s in enumerate(stages):
-                    R.stage(s, b)
-                    e[k + 1].record(stream)
-                ev.append(e)
-            else:
-                R.stage("sd7_render", b)
-
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        step(record=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    dt = t1 - t0
+    # default-priority streams the batches of a step alternate over
+    streams = [stream] + [torch.cuda.Stream() for _ in range(max(1, a.streams) - 1)]
+    run_steps(R, batches, a.warmup, streams)
+    dt, raster_ms = run_steps(R, batches, a.steps, streams, record_stage="sd7_rasterize")
     nframes = len(views) * a.steps
     fps = nframes / dt
     # correctness of the timed run: no frame overflowed its arena
@@ -279,15 +294,13 @@ def main():
         bc = R.batch(fc, b.capacity)
         R.stage("sd7_render", bc)
         contribs += sum(int(fr.ncontrib.to(torch.int64).sum()) for fr in fc)
-    stage_ms = {s: [] for s in stages}
-    for e in ev:
-        for k, s in enumerate(stages):
-            stage_ms[s].append(e[k].elapsed_time(e[k + 1]))
-    stage_avg = {s: float(np.mean(v)) for s, v in stage_ms.items()}
-    per_step_stage = {s: stage_avg[s] * len(batches) for s in stages}
+    per_step_stage = serial_stage_ms(R, batches, 2)
 
-    # -- roofline of the dominant kernel (the rasterizer)
-    t_r = stage_avg["sd7_rasterize"] * 1e-3                        # per batch launch, s
+    # -- roofline of the dominant kernel (the rasterizer): its launches in the
+    # timed region, HIP events on their own stream (other batches' stages run
+    # alongside)
+    raster_launch_ms = float(np.mean(raster_ms))
+    t_r = raster_launch_ms * 1e-3                                  # per batch launch, s
     evals_l = evals / len(batches)
     current = RASTER_SRC_SHA256 is not None and raster_src_digest() == RASTER_SRC_SHA256
     tests_l, contribs_l = tests / len(batches), contribs / len(batches)
@@ -304,7 +317,7 @@ def main():
                                       "wave_evaluations_per_launch": int(evals_l)},
                 "counters_current": current,
                 "valu_instructions_per_launch": RASTER_VALU_INSTRUCTIONS if current else None,
-                "avg_launch_ms": round(stage_avg["sd7_rasterize"], 4)}
+                "avg_launch_ms": round(raster_launch_ms, 4)}
 
     # -- latency: batched (frames of a batch finish with their batch) vs plain
     lat_batched = []
@@ -339,7 +352,7 @@ def main():
                          f"brute-force compositing), {tc:.2f} s; FPS extrapolated to the full 800x800 frame"}
 
     serving = serve_bench(a, R, L) if a.serve else None
-    agr = agr_bench(a, R, L, scene, views) if a.agr else None
+    agr = agr_bench(a, R, L, scene, views, streams) if a.agr else None
 
     out = {
         "metric": "rendered FPS and Mpixel/s at 1 GPU; p50/p99 frame latency, batched vs plain",
@@ -348,12 +361,12 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "200k 7D Gaussians, 50 views 800x800, forward (slice, project, bin, raster)",
                    "gaussians": scene.n, "views": len(views), "resolution": [W, H],
-                   "batch": a.batch, "parallelism": "single GPU"},
+                   "batch": a.batch, "streams": a.streams, "parallelism": "single GPU"},
         "mpixel_per_s": round(fps * W * H / 1e6, 1),
         "latency_ms": {"batched_p50": pct(lat_batched, 50), "batched_p99": pct(lat_batched, 99),
                        "plain_p50": pct(lat_plain, 50), "plain_p99": pct(lat_plain, 99)},
         "plain_fps": round(plain_fps, 2) if plain_fps else None,
-        "stage_ms_per_step": {k: round(v, 4) for k, v in per_step_stage.items()},
+        "stage_ms_per_step": per_step_stage,
         "pairs_per_view_mean": int(np.mean(pairs)), "overflowed_frames": overflow,
         "roofline": roofline,
         "cpu_baseline": cpu,
