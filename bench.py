@@ -45,8 +45,8 @@ FP32_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 RASTER_OPS_PER_TEST = 12
 RASTER_OPS_PER_CONTRIBUTION = 12
 RASTER_SRC = ("paper_2503_07946_amd/csrc/raster.hip", "paper_2503_07946_amd/csrc/common.h")
-RASTER_SRC_SHA256 = "e6304134324d84557c56238ab3fa71cc23ff7871154cf073cbd9961770f9e862"
-RASTER_TRAFFIC_BYTES = 2420979920       # (1025869 KiB x 2 + 312500 KiB) x 1024
+RASTER_SRC_SHA256 = "063f2548f7498d91850055f61e60330cd3ae28b717d6d93342e9ec4441d05efc"
+RASTER_TRAFFIC_BYTES = 2422288672       # (1026508 KiB x 2 + 312500 KiB) x 1024
 RASTER_VALU_INSTRUCTIONS = 1133839814   # SQ_INSTS_VALU per launch (wave64 instructions)
 
 
