@@ -122,15 +122,17 @@ __device__ __forceinline__ bool project_one(const FrameDev& F, const float m[3],
 }
 
 // Row trims of a footprint (the layout is described with Footprint): for the
-// tile rows it stores, the tiles at either end of the row that the ellipse
-// q <= k misses.  q is evaluated through the 2D covariance: at row offset dy
-// the ellipse spans dx = dy s01 / s11 +- sqrt((k - dy^2 / s11) det / s11); on
-// a tile row's strip of dy the left end is least at the clamp of the leftmost
-// point's dy into the strip, the right end greatest at the clamp of the
-// rightmost point's.  k is raised by 1/16 of itself plus 1/4, which covers the
-// hardware square root and reciprocal used here and the rasterizer's FP32
-// exponent; a box one tile wide or high, or an ill-conditioned covariance,
-// gets no trims.
+// tile rows it stores, the tiles at either end of the row none of whose pixel
+// centres the ellipse q <= k reaches.  The test runs on pixel centres: tile
+// row ty's centres lie on the strip y in [16 ty + 1/2, 16 ty + 31/2], tile
+// column tx's on x in [16 tx + 1/2, 16 tx + 31/2].  q is evaluated through
+// the 2D covariance: at row offset dy the ellipse spans dx = dy s01 / s11 +-
+// sqrt((k - dy^2 / s11) det / s11); on a strip of dy the left end is least at
+// the clamp of the leftmost point's dy into the strip, the right end greatest
+// at the clamp of the rightmost point's.  k is raised by 0.2 % plus 0.02 (in
+// log2 of alpha, 3 % of headroom), well above the error of the hardware square
+// root and reciprocal used here and of the rasterizer's FP32 exponent; a box
+// one tile wide or high, or an ill-conditioned covariance, gets no trims.
 __device__ __forceinline__ uint2 footprint_trims(const Proj& p, float k, uint32_t rx0, uint32_t ry0, uint32_t rx1,
                                                  uint32_t ry1)
 {
@@ -139,7 +141,7 @@ __device__ __forceinline__ uint2 footprint_trims(const Proj& p, float k, uint32_
     if (w < 2 || h < 2 || !(tr * tr < 1e6f * p.det)) return make_uint2(0u, 0u);
     const uint32_t m = h > 8 ? h - 4 : 4;  // first of the bottom rows
     const uint32_t nrow = min(h, 8u);
-    const float km = fmaf(k, 1.0625f, 0.25f);
+    const float km = fmaf(k, 1.002f, 0.02f);
     const float r11 = __builtin_amdgcn_rcpf(p.s11);
     const float slope = p.s01 * r11, wsq = p.det * r11;
     const float dyx = p.s01 * __builtin_amdgcn_sqrtf(km * __builtin_amdgcn_rcpf(p.s00));  // rightmost point; leftmost at -dyx
@@ -148,16 +150,17 @@ __device__ __forceinline__ uint2 footprint_trims(const Proj& p, float k, uint32_
     uint32_t word[2] = {0u, 0u};
     for (uint32_t q = 0; q < nrow; ++q) {
         const uint32_t r = q < 4 ? q : m + (q - 4);
-        const float y = (float)((ry0 + r) * kTile) - p.v;
-        const float dya = fmaxf(y, -hy), dyb = fminf(y + (float)kTile, hy);
+        const float y = (float)((ry0 + r) * kTile) + 0.5f - p.v;
+        const float dya = fmaxf(y, -hy), dyb = fminf(y + (float)(kTile - 1), hy);
         const float yl = fminf(fmaxf(-dyx, dya), dyb), yr = fminf(fmaxf(dyx, dya), dyb);
         const float xl = fmaf(slope, yl, p.u) - __builtin_amdgcn_sqrtf(fmaxf(fmaf(-yl * r11, yl, km), 0.0f) * wsq);
         const float xr = fmaf(slope, yr, p.u) + __builtin_amdgcn_sqrtf(fmaxf(fmaf(-yr * r11, yr, km), 0.0f) * wsq);
-        // tiles left of the one holding xl and right of the one holding xr; a
-        // strip that misses the ellipse empties the row (as far as 15 + 15
-        // tiles go); NaN keeps the row whole (fmaxf returns the other operand)
-        float lt = fminf(fmaxf(floorf(xl * inv_tile) - (float)rx0, 0.0f), 15.0f);
-        float rt = fminf(fmaxf((float)(rx1 - 1) - floorf(xr * inv_tile), 0.0f), 15.0f);
+        // tiles whose last centre column lies left of xl, or whose first lies
+        // right of xr; a strip that misses the ellipse empties the row (as
+        // far as 15 + 15 tiles go); NaN keeps the row whole (fmaxf returns the
+        // other operand)
+        float lt = fminf(fmaxf(ceilf((xl - (float)kTile + 0.5f) * inv_tile) - (float)rx0, 0.0f), 15.0f);
+        float rt = fminf(fmaxf((float)(rx1 - 1) - floorf((xr - 0.5f) * inv_tile), 0.0f), 15.0f);
         if (!(dya <= dyb)) {
             lt = fminf((float)w, 15.0f);
             rt = fminf((float)w - lt, 15.0f);
