@@ -39,12 +39,13 @@ FP32_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 # the pixel -- 12 more: 2^p and the 0.99 clamp (2), T' = T (1 - alpha) (2),
 # the stop test (1), w = T alpha (1) and three colour FMAs (6).  Traffic:
 # FETCH_SIZE x 2 + WRITE_SIZE (KiB x 1024) per launch, scaling factors from a
-# 1 GiB device copy, taken for the kernel source whose digest is
-# RASTER_SRC_SHA256 (null once the source differs), with the VALU instruction
-# count of the same runs.
+# 1 GiB device copy, with the VALU instruction count of the same runs.  They
+# hold for the library source whose digest is RASTER_SRC_SHA256 -- every
+# kernel source, since the splat records and tile lists the rasterizer walks
+# come from the other stages -- and are dropped (null) once it differs.
 RASTER_OPS_PER_TEST = 12
 RASTER_OPS_PER_CONTRIBUTION = 12
-RASTER_SRC = ("paper_2503_07946_amd/csrc/raster.hip", "paper_2503_07946_amd/csrc/common.h")
+RASTER_SRC_DIR = "paper_2503_07946_amd/csrc"
 RASTER_SRC_SHA256 = "063f2548f7498d91850055f61e60330cd3ae28b717d6d93342e9ec4441d05efc"
 RASTER_TRAFFIC_BYTES = 2422288672       # (1026508 KiB x 2 + 312500 KiB) x 1024
 RASTER_VALU_INSTRUCTIONS = 1133839814   # SQ_INSTS_VALU per launch (wave64 instructions)
@@ -53,9 +54,12 @@ RASTER_VALU_INSTRUCTIONS = 1133839814   # SQ_INSTS_VALU per launch (wave64 instr
 def raster_src_digest() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in RASTER_SRC:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+    d = os.path.join(ROOT, RASTER_SRC_DIR)
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()
 
 
