@@ -222,8 +222,8 @@ def agr_bench(a, R, L, scene, views, streams):
     for gv in groups:
         frames = R.make_frames([(gs, v) for v in gv])
         c = R.read_counts(R.render_frames(frames, exact=True))
-        need = int(sum((int(p) + 4095) // 4096 * 4096 for p in c[:, L.SD7_CNT_NEEDED]))
-        batches.append(R.batch(frames, int(need * 1.05) + 4096))
+        need = int(sum(-(-int(p) // L.SD7_PAIR_ROUND) * L.SD7_PAIR_ROUND for p in c[:, L.SD7_CNT_NEEDED]))
+        batches.append(R.batch(frames, int(need * 1.05) + L.SD7_PAIR_ROUND))
     run_steps(R, batches, a.warmup, streams)
     dt, _ = run_steps(R, batches, a.steps, streams)
     over = sum(int(np.sum(R.read_counts(b)[:, L.SD7_CNT_FLAGS] & L.SD7_FLAG_PAIR_OVERFLOW != 0)) for b in batches)
@@ -269,8 +269,8 @@ def main():
         frames = R.make_frames([(gs, v) for v in gv])
         b0 = R.render_frames(frames, exact=True)
         c = R.read_counts(b0)
-        need = int(sum((int(p) + 4095) // 4096 * 4096 for p in c[:, L.SD7_CNT_NEEDED]))
-        cap = int(need * 1.05) + 4096
+        need = int(sum(-(-int(p) // L.SD7_PAIR_ROUND) * L.SD7_PAIR_ROUND for p in c[:, L.SD7_CNT_NEEDED]))
+        cap = int(need * 1.05) + L.SD7_PAIR_ROUND
         batches.append(R.batch(frames, cap))
     torch.cuda.synchronize()
 

@@ -81,6 +81,7 @@ typedef int32_t sd7_status;
 #define SD7_MAX_FRAMES 64
 #define SD7_TILE 16
 #define SD7_MAX_DIM 16384
+#define SD7_PAIR_ROUND 2048 /* a frame's share of the pair arena is a multiple of this */
 
 /* per-frame device flags (bitmask) */
 #define SD7_FLAG_NONPOS_DIAG 1u   /* some L has a diagonal entry <= 0 (Gaussian culled) */
@@ -306,7 +307,7 @@ const char* sd7_last_error(void);
 
 /* Host only.  Workspace size and layout for these frames and a pair arena of
  * `pair_capacity` (tile, Gaussian) pairs shared by all frames (each frame's
- * share is rounded up to a multiple of 4096 pairs).  Checks the frames:
+ * share is rounded up to a multiple of SD7_PAIR_ROUND pairs).  Checks the frames:
  * 1 <= nf <= SD7_MAX_FRAMES, 0 <= n < 2^31, 1 <= W, H <= SD7_MAX_DIM, total
  * Gaussians and tiles < 2^31, pair_capacity < 2^31, non-null scene arrays
  * when n > 0, non-null image/final_T/last.  Returns SD7_EINVAL otherwise. */

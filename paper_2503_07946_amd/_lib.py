@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(PKG, "lib7dgs.so")
 SD7_OK, SD7_EINVAL, SD7_EHIP, SD7_EWORKSPACE, SD7_ENOMEM = 0, -1, -2, -3, -4
 SD7_MAX_FRAMES = 64
 SD7_TILE = 16
+SD7_PAIR_ROUND = 2048       # a frame's arena share is a multiple of this (sd7.h)
 SD7_FLAG_NONPOS_DIAG, SD7_FLAG_NONFINITE, SD7_FLAG_PAIR_OVERFLOW = 1, 2, 4
 SD7_CNT_KEPT, SD7_CNT_PAIRS, SD7_CNT_PAIR_BASE, SD7_CNT_FLAGS = 0, 1, 2, 3
 SD7_CNT_NEEDED = 4          # pairs the frame needed (internal word, also set on overflow)

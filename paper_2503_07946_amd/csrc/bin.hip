@@ -241,11 +241,11 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
         s_goff[tid] = hist[256u * sg.wt0 + tid * sg.nwt + k] - sg.cnt_excl + sg.out_base;
         s_wh[0][tid] = 0; s_wh[1][tid] = 0; s_wh[2][tid] = 0; s_wh[3][tid] = 0;
         __syncthreads();
-        const uint32_t wbase = k * kSortItems + wave * 1024;
-        uint32_t key[16], val[16], rank[16];
+        const uint32_t wbase = k * kSortItems + wave * (kSortPerThread * 64);
+        uint32_t key[kSortPerThread], val[kSortPerThread], rank[kSortPerThread];
         uint32_t okmask = 0;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
+        for (int r = 0; r < kSortPerThread; ++r) {
             const uint32_t e = wbase + r * 64 + lane;
             bool ok = e < sg.len;
             const uint32_t kk = ok ? keys_in[sg.in_base + e] : 0u;
@@ -280,7 +280,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
+        for (int r = 0; r < kSortPerThread; ++r) {
             if ((okmask >> r) & 1u) {
                 const uint32_t d = (key[r] >> shift) & 255u;
                 const uint32_t p = s_goff[d] + s_wh[wave][d] + rank[r];
@@ -473,7 +473,7 @@ __global__ __launch_bounds__(256) void k_emit(const FrameDev* __restrict__ tab, 
         const uint32_t k = w - sg.wt0;
         const uint32_t t_begin = k * kSortItems;
         const uint32_t cnt = min((uint32_t)kSortItems, sg.len - t_begin);
-        const uint32_t o0 = t_begin + threadIdx.x * 16;
+        const uint32_t o0 = t_begin + threadIdx.x * kSortPerThread;
         const uint32_t* tf = toff + F.g0;
         const uint32_t* of = order + F.g0;
         if (o0 < sg.len) {
@@ -489,7 +489,7 @@ __global__ __launch_bounds__(256) void k_emit(const FrameDev* __restrict__ tab, 
             uint4 rc = rect[F.g0 + of[j]];
             uint32_t g = of[j];
 #pragma unroll 1
-            for (int r = 0; r < 16; ++r) {
+            for (int r = 0; r < kSortPerThread; ++r) {
                 const uint32_t o = o0 + r;
                 if (o >= sg.len) break;
                 while (o >= next) {
@@ -499,8 +499,8 @@ __global__ __launch_bounds__(256) void k_emit(const FrameDev* __restrict__ tab, 
                     g = of[j];
                     rc = rect[F.g0 + g];
                 }
-                s_t[threadIdx.x * 16 + r] = footprint_tile(Footprint(rc), o - start, F.tiles_x);
-                s_g[threadIdx.x * 16 + r] = g;
+                s_t[threadIdx.x * kSortPerThread + r] = footprint_tile(Footprint(rc), o - start, F.tiles_x);
+                s_g[threadIdx.x * kSortPerThread + r] = g;
             }
         }
         __syncthreads();

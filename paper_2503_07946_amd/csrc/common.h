@@ -23,7 +23,9 @@ constexpr float kNegHalfLog2e = -0.72134752044448170f;
 constexpr float kNegLog2e = -1.4426950408889634f;
 
 constexpr int kBlock = 256;        // threads per block of the per-Gaussian kernels
-constexpr int kSortItems = 4096;   // elements per radix-sort work tile (256 threads x 16)
+constexpr int kSortPerThread = 8;  // radix-sort elements per thread of a work tile
+constexpr int kSortItems = 256 * kSortPerThread;  // elements per radix-sort work tile
+static_assert(kSortItems == SD7_PAIR_ROUND, "a frame's arena share is a whole number of work tiles");
 constexpr int kScanItems = 4096;   // elements per scan work tile
 constexpr int kSplatFloats = 12;   // floats per splat record
 

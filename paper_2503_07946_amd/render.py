@@ -257,7 +257,7 @@ class Renderer:
         if exact:
             c = self.read_counts(b, stream)
             if np.any(c[:, L.SD7_CNT_FLAGS] & L.SD7_FLAG_PAIR_OVERFLOW):
-                need = int(sum((int(x) + 4095) // 4096 * 4096 for x in c[:, L.SD7_CNT_NEEDED]))
+                need = int(sum(-(-int(x) // L.SD7_PAIR_ROUND) * L.SD7_PAIR_ROUND for x in c[:, L.SD7_CNT_NEEDED]))
                 b2 = self.batch(frames, need)
                 prefix = int(b.layout.off_pair_g)
                 b2.ws[:prefix].copy_(b.ws[:prefix])

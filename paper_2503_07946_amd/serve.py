@@ -23,7 +23,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-PAIR_ROUND = 4096
+PAIR_ROUND = 2048  # the library's SD7_PAIR_ROUND: a frame's arena share is a multiple of it
 
 
 @dataclass(eq=False)       # a request is itself: compared by identity

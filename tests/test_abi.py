@@ -39,6 +39,15 @@ def test_struct_sizes_match_the_header_layout():
     assert ctypes.sizeof(L.Sd7Frame) == 64 + 112 + 4 * 8 + 7 * 8 + 8
 
 
+def test_constants_match_the_header():
+    from paper_2503_07946_amd import serve
+    defines = dict(re.findall(r"#define (SD7_[A-Z_]+) \(?(-?\d+)u?\)?", open(HEADER).read()))
+    for name in ("SD7_MAX_FRAMES", "SD7_TILE", "SD7_PAIR_ROUND", "SD7_CNT_KEPT", "SD7_CNT_PAIRS",
+                 "SD7_CNT_PAIR_BASE", "SD7_CNT_FLAGS", "SD7_CNT_WORDS", "SD7_AGR_WEIGHTS"):
+        assert int(defines[name]) == getattr(L, name), name
+    assert serve.PAIR_ROUND == L.SD7_PAIR_ROUND
+
+
 def _frame(n=100, W=64, H=48, ptr=0x1000):
     f = L.Sd7Frame()
     p = ctypes.c_void_p(ptr)

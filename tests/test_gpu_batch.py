@@ -50,7 +50,7 @@ def test_batch_overflow_defers_only_frames_that_do_not_fit(R):
     g = GaussianScene.from_host(s)
     alone = R.render_frames(R.make_frames([(g, v[0])]))
     P = int(R.read_counts(alone)[0, L.SD7_CNT_PAIRS])
-    cap = ((P + 4095) // 4096) * 4096      # room for exactly one frame
+    cap = -(-P // L.SD7_PAIR_ROUND) * L.SD7_PAIR_ROUND      # room for exactly one frame
     b = R.render_frames(R.make_frames([(g, v[0]), (g, v[0])]), capacity=cap, exact=False)
     c = R.read_counts(b)
     assert not c[0, L.SD7_CNT_FLAGS] & L.SD7_FLAG_PAIR_OVERFLOW
