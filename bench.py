@@ -186,6 +186,25 @@ def run_steps(R, batches, steps, streams, record_stage=None):
     return dt, [e0.elapsed_time(e1) for e0, e1 in ev]
 
 
+def stage_hbm_fracs(stage_ms, n, views, batch, kept, pairs, tiles):
+    """Algorithmic HBM bytes of a step's slice + project and binning stages and
+    the fraction of the 8 TB/s peak their serial times reach.  Slice + project:
+    the 336 B of scene parameters read once per run of up to 16 frames sharing
+    the scene, and per (Gaussian, frame) the 108 B written (sliced mean,
+    covariance and opacity 40 B, splat record 48 B, footprint 16 B, depth key
+    4 B).  Binning: the depth sort's 64 B per kept Gaussian (four passes, each
+    reading and writing a key and a value), 4 B per pair of the tile lists and
+    8 B per tile range."""
+    runs = views // batch * -(-batch // 16) + (-(-(views % batch) // 16) if views % batch else 0)
+    out = {}
+    for name, b in (("sd7_slice_project", 336 * n * runs + 108 * n * views),
+                    ("sd7_bin", 64 * kept + 4 * pairs + 8 * tiles)):
+        t = stage_ms[name] * 1e-3
+        out[name] = {"algorithmic_bytes": int(b), "gb_s": round(b / t / 1e9, 1),
+                     "frac": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def serial_stage_ms(R, batches, reps):
     """Per-step milliseconds of each stage, one stream, no overlap."""
     import numpy as np
@@ -283,12 +302,14 @@ def main():
     # correctness of the timed run: no frame overflowed its arena
     overflow = 0
     pairs = []
+    kept = []
     tests = contribs = 0
     evals = 0
     for b in batches:
         c = R.read_counts(b)
         overflow += int(np.sum(c[:, L.SD7_CNT_FLAGS] & L.SD7_FLAG_PAIR_OVERFLOW != 0))
         pairs += [int(x) for x in c[:, L.SD7_CNT_PAIRS]]
+        kept += [int(x) for x in c[:, L.SD7_CNT_KEPT]]
         for f, fr in enumerate(b.frames):
             tests += int(fr.last.to(torch.int64).sum())
             evals += wave_evaluations(fr.last, b.ranges(f), fr.view.W, fr.view.H)
@@ -299,6 +320,8 @@ def main():
         R.stage("sd7_render", bc)
         contribs += sum(int(fr.ncontrib.to(torch.int64).sum()) for fr in fc)
     per_step_stage = serial_stage_ms(R, batches, 2)
+    stage_hbm = stage_hbm_fracs(per_step_stage, scene.n, len(views), a.batch, sum(kept), sum(pairs),
+                                len(views) * ((W + 15) // 16) * ((H + 15) // 16))
 
     # -- roofline of the dominant kernel (the rasterizer): its launches in the
     # timed region, HIP events on their own stream (other batches' stages run
@@ -371,7 +394,9 @@ def main():
                        "plain_p50": pct(lat_plain, 50), "plain_p99": pct(lat_plain, 99)},
         "plain_fps": round(plain_fps, 2) if plain_fps else None,
         "stage_ms_per_step": per_step_stage,
-        "pairs_per_view_mean": int(np.mean(pairs)), "overflowed_frames": overflow,
+        "pairs_per_view_mean": int(np.mean(pairs)), "kept_per_view_mean": int(np.mean(kept)),
+        "overflowed_frames": overflow,
+        "stage_hbm": stage_hbm,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "serving": serving,

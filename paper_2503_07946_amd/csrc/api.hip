@@ -304,6 +304,8 @@ sd7_status upload_table(sd7_ctx* ctx, const sd7_frame* fr, int nf, const Plan& P
         D.t = F.view.t;
         std::memcpy(D.d, F.view.d, sizeof(D.d));
         D.lambda_t = F.view.lambda_t; D.lambda_d = F.view.lambda_d;
+        D.limx = kJClamp * (0.5f * (float)F.view.W) / F.view.fx;
+        D.limy = kJClamp * (0.5f * (float)F.view.H) / F.view.fy;
         std::memcpy(D.bg, F.view.bg, sizeof(D.bg));
     }
     HIP_TRY(hipMemcpyAsync(ws + P.L.off_table, tab, sizeof(FrameDev) * nf, hipMemcpyHostToDevice, st));

@@ -65,7 +65,7 @@ struct FrameDev {
     float d[3];
     float lambda_t, lambda_d;
     float bg[3];
-    float pad1[2];
+    float limx, limy;  // view-ray ratio clamps of J: 1.3 x (W/2) / fx, 1.3 x (H/2) / fy
 };
 
 constexpr uint32_t kMaxCountTiles = 32768;  // tiles per frame the counting binner takes (more: radix binner)

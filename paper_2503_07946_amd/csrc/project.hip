@@ -86,18 +86,18 @@ __device__ __forceinline__ bool project_one(const FrameDev& F, const float m[3],
     const float z = p.x[2];
     if (!(z > kZNear)) return false;
     const float fx = F.fx, fy = F.fy;
-    p.u = fx * p.x[0] / z + F.cx;
-    p.v = fy * p.x[1] / z + F.cy;
-    const float limx = kJClamp * (0.5f * (float)F.W) / fx;
-    const float limy = kJClamp * (0.5f * (float)F.H) / fy;
-    float rx = p.x[0] / z, ry = p.x[1] / z;
+    const float iz = __builtin_amdgcn_rcpf(z);  // hardware reciprocal: z > 0.2, error about 1 ulp
+    p.u = fmaf(fx * p.x[0], iz, F.cx);
+    p.v = fmaf(fy * p.x[1], iz, F.cy);
+    const float limx = F.limx, limy = F.limy;
+    float rx = p.x[0] * iz, ry = p.x[1] * iz;
     p.clx = rx >= limx || rx <= -limx;
     p.cly = ry >= limy || ry <= -limy;
     rx = fminf(fmaxf(rx, -limx), limx);
     ry = fminf(fmaxf(ry, -limy), limy);
     p.rx = rx;
     p.ry = ry;
-    const float j00 = fx / z, j02 = -fx * rx / z, j11 = fy / z, j12 = -fy * ry / z;
+    const float j00 = fx * iz, j02 = -fx * rx * iz, j11 = fy * iz, j12 = -fy * ry * iz;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         p.M[0][k] = j00 * F.R[k] + j02 * F.R[6 + k];
@@ -115,9 +115,10 @@ __device__ __forceinline__ bool project_one(const FrameDev& F, const float m[3],
     p.s11 = T[1][0] * p.M[1][0] + T[1][1] * p.M[1][1] + T[1][2] * p.M[1][2] + kDilation;
     p.det = p.s00 * p.s11 - p.s01 * p.s01;
     if (!(p.det > 0.0f)) return false;
-    p.a = p.s11 / p.det;
-    p.b = -p.s01 / p.det;
-    p.c = p.s00 / p.det;
+    const float idet = __builtin_amdgcn_rcpf(p.det);
+    p.a = p.s11 * idet;
+    p.b = -p.s01 * idet;
+    p.c = p.s00 * idet;
     return true;
 }
 
@@ -191,8 +192,8 @@ __device__ __forceinline__ bool project_emit(const FrameDev& F, uint32_t i, floa
     uint32_t rx0 = 0, ry0 = 0, rx1 = 0, ry1 = 0;
     uint2 trims = make_uint2(0u, 0u);
     if (keep) {
-        const float k = 2.0f * logf(ac / kAlphaMin);
-        const float hx = sqrtf(k * p.s00), hy = sqrtf(k * p.s11);
+        const float k = 2.0f * logf(ac * 255.0f);
+        const float hx = __builtin_amdgcn_sqrtf(k * p.s00), hy = __builtin_amdgcn_sqrtf(k * p.s11);
         float tx0 = floorf((p.u - hx) / (float)kTile), tx1 = floorf((p.u + hx) / (float)kTile);
         float ty0 = floorf((p.v - hy) / (float)kTile), ty1 = floorf((p.v + hy) / (float)kTile);
         tx0 = fmaxf(tx0, 0.0f);
@@ -209,7 +210,7 @@ __device__ __forceinline__ bool project_emit(const FrameDev& F, uint32_t i, floa
     float rgb[3] = {0.f, 0.f, 0.f};
     if (keep) {
         const float dx = m[0] - F.c[0], dy = m[1] - F.c[1], dz = m[2] - F.c[2];
-        const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+        const float inv = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
         float Y[16];
         sh_eval(dx * inv, dy * inv, dz * inv, Y);
 #pragma unroll

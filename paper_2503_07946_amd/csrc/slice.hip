@@ -248,7 +248,16 @@ __device__ __forceinline__ void slice_outputs(const SliceFixed& S, const SliceVi
         for (int k = 0; k < 4; ++k) s = fma(S.V[a][k], W.u[k], s);
         m[a] = s;
     }
-    double a_c = (double)alpha * exp(-0.5 * (W.e_t + W.e_d));
+    // e^{-(e_t + e_d)/2} = 2^t = 2^n 2^f with n = floor(t) and f = t - n in
+    // [0, 1) exact in FP64; 2^f from the hardware exp2 in FP32 (relative
+    // error about 1e-7, below the FP32 rounding of alpha_c); NaN passes on.
+    const double t = -0.5 * 1.4426950408889634 * (W.e_t + W.e_d);
+    double a_c = t;
+    if (t == t) {
+        const double n = floor(fmin(fmax(t, -1100.0), 1100.0));
+        const float f = (float)(fmin(fmax(t, -1100.0), 1100.0) - n);
+        a_c = ldexp((double)alpha * (double)__builtin_amdgcn_exp2f(f), (int)n);
+    }
     const bool fin = isfinite(m[0]) && isfinite(m[1]) && isfinite(m[2]) && isfinite(a_c) && cv_fin;
     if (S.ok && !fin) flag |= SD7_FLAG_NONFINITE;
     if (!S.ok && !(flag & SD7_FLAG_NONPOS_DIAG)) flag |= SD7_FLAG_NONFINITE;
