@@ -46,9 +46,9 @@ FP32_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 RASTER_OPS_PER_TEST = 12
 RASTER_OPS_PER_CONTRIBUTION = 12
 RASTER_SRC_DIR = "paper_2503_07946_amd/csrc"
-RASTER_SRC_SHA256 = "063f2548f7498d91850055f61e60330cd3ae28b717d6d93342e9ec4441d05efc"
-RASTER_TRAFFIC_BYTES = 2422288672       # (1026508 KiB x 2 + 312500 KiB) x 1024
-RASTER_VALU_INSTRUCTIONS = 1133839814   # SQ_INSTS_VALU per launch (wave64 instructions)
+RASTER_SRC_SHA256 = "84ee5da4ab13eeae1360f54b603e80b0cb8d148004a5348fbd2e8c10720d20bf"
+RASTER_TRAFFIC_BYTES = 2344137930       # (988349 KiB x 2 + 312500 KiB) x 1024
+RASTER_VALU_INSTRUCTIONS = 1108255228   # SQ_INSTS_VALU per launch (wave64 instructions)
 
 
 def raster_src_digest() -> str:
