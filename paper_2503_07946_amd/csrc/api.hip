@@ -61,6 +61,7 @@ struct Scratch {
     size_t pt_a, pt_b, pg_b;         // radix tile sort: tile keys and ping-pong buffers
     size_t toff;                     // tile offsets (scan of tiles per sorted Gaussian)
     size_t srect;                    // footprints in depth order (counting binner)
+    size_t sspan;                    // their tile-group spans (counting binner)
     size_t segs_all, segs_kept, segs_pairs;
     size_t tot_all, tot_kept, tot_pairs;
     size_t hist, partials, words;
@@ -91,7 +92,7 @@ struct Plan {
 };
 
 constexpr uint64_t kBinWaves = 131072; // (chunk, group) waves the counting binner aims for per call
-constexpr uint64_t kMaxChunks = 128;   // chunks per frame (the depth of the per-tile column scan)
+constexpr uint64_t kMaxChunks = 512;   // chunks per frame (the depth of the per-tile column scan)
 constexpr size_t kMaxMatrix = (size_t)1 << 28;  // count-matrix entries of one call
 
 // Binning chunks per frame: enough (chunk, group) waves over the call to fill
@@ -236,6 +237,7 @@ sd7_status make_plan(const sd7_frame* fr, int nf, int64_t cap, Plan& P, bool nee
     S.pg_b = take(4 * CR);
     S.toff = take(4 * (N + 16));
     S.srect = take(16 * (P.counting ? N : 0));
+    S.sspan = take(4 * (P.counting ? N : 0));
     S.segs_all = take(sizeof(SortSeg) * nf);
     S.segs_kept = take(sizeof(SortSeg) * nf);
     S.segs_pairs = take(sizeof(SortSeg) * nf);
@@ -501,7 +503,8 @@ sd7_status do_bin(const Call& c)
     if (c.P.gblocks) {
         k_gather_ntiles<<<c.P.gblocks, kBlock, 0, c.st>>>(c.tab, c.P.gmap, c.counts, order,
                                                           c.at<uint4>(L.off_rect), toff,
-                                                          c.P.counting ? c.at<uint4>(S.srect) : nullptr);
+                                                          c.P.counting ? c.at<uint4>(S.srect) : nullptr,
+                                                          c.P.counting ? c.at<uint32_t>(S.sspan) : nullptr);
         LAUNCH_CHECK("k_gather_ntiles");
     }
     const uint32_t ntot = (uint32_t)L.n_total;
@@ -526,7 +529,8 @@ sd7_status do_bin(const Call& c)
         LAUNCH_CHECK("k_tile_colscan");
         if ((s = scan(c, ttot, ttiles, nullptr, ttiles, nullptr)) != SD7_OK) return s;
         if (c.P.cblocks) {
-            k_group_place<<<c.P.cblocks, 64, 0, c.st>>>(c.tab, c.P.cmap, c.counts, order, srect, cnt, ttot,
+            k_group_place<<<c.P.cblocks, 64, 0, c.st>>>(c.tab, c.P.cmap, c.counts, order, srect,
+                                                         c.at<uint32_t>(S.sspan), cnt, ttot,
                                                          c.at<uint32_t>(L.off_pair_g));
             LAUNCH_CHECK("k_group_place");
         }

@@ -18,6 +18,7 @@
 // the kernels that need them run persistent grids over work tiles.
 #include "common.h"
 #include "footprint.h"
+#include "gload.h"
 
 namespace sd7 {
 
@@ -341,15 +342,73 @@ __global__ __launch_bounds__(64) void k_setup_depth(const FrameDev* __restrict__
     }
 }
 
+// The counting binner's copy of a footprint.  A box of at most kMaskSide x
+// kMaskSide tiles keeps its covered tiles as a bit mask in z (rows 0..3) and w
+// (rows 4..7), bit 8 * row + column; a larger box keeps the row trims of its
+// footprint.  x and y (the box) are as in the footprint.
+constexpr uint32_t kMaskSide = 8;
+
+__device__ __forceinline__ bool is_mask_box(uint32_t x, uint32_t y)
+{
+    return (y & 0xFFFFu) - (x & 0xFFFFu) <= kMaskSide && (y >> 16) - (x >> 16) <= kMaskSide;
+}
+
+__device__ __forceinline__ uint4 bin_box(uint4 f)
+{
+    if (!is_mask_box(f.x, f.y)) return f;
+    const Footprint fp(f);
+    uint64_t m = 0;
+    for (uint32_t r = 0; r < fp.h(); ++r) {
+        int a, b;
+        fp.row(r, a, b);
+        if (a < b) m |= (((1ull << (b - a)) - 1ull) << (a - (int)fp.x0)) << (kMaskSide * r);
+    }
+    return make_uint4(f.x, f.y, (uint32_t)m, (uint32_t)(m >> 32));
+}
+
+// Tile columns [a, b) of row r (0 <= r < h) of a binner box; empty when a >= b.
+__device__ __forceinline__ void bin_box_row(uint4 bb, uint32_t r, int& a, int& b)
+{
+    if (!is_mask_box(bb.x, bb.y)) {
+        Footprint(bb).row(r, a, b);
+        return;
+    }
+    const int x0 = (int)(bb.x & 0xFFFFu);
+    const uint32_t bits = ((r < 4 ? bb.z : bb.w) >> (8 * (r & 3u))) & 0xFFu;
+    a = x0 + (int)__builtin_ctz(bits | 0x100u);
+    b = x0 + 32 - (int)__builtin_clz(bits | 1u);
+    if (bits == 0) b = a;
+}
+
+// Tile groups (kGroup x kGroup tiles) that the bounding box of a footprint
+// meets, as bytes gx0 | (gx1 - gx0) << 8 | gy0 << 16 | (gy1 - gy0) << 24 with
+// inclusive ends.  An empty box packs to all ones, which meets no group of a
+// frame of at most 255 * kGroup tiles per side.
+__device__ __forceinline__ uint32_t group_span(uint4 r)
+{
+    const uint32_t x0 = r.x & 0xFFFFu, y0 = r.x >> 16, x1 = r.y & 0xFFFFu, y1 = r.y >> 16;
+    if (x0 >= x1 || y0 >= y1) return 0xFFFFFFFFu;
+    const uint32_t gx0 = x0 / kGroup, gx1 = (x1 - 1) / kGroup;
+    const uint32_t gy0 = y0 / kGroup, gy1 = (y1 - 1) / kGroup;
+    return gx0 | (gx1 - gx0) << 8 | gy0 << 16 | (gy1 - gy0) << 24;
+}
+
+// Whether group (gx, gy) lies in a packed group span.
+__device__ __forceinline__ bool span_meets(uint32_t d, uint32_t gx, uint32_t gy)
+{
+    return (gx - (d & 0xFFu) <= ((d >> 8) & 0xFFu)) & (gy - ((d >> 16) & 0xFFu) <= (d >> 24));
+}
+
 // Tiles of each Gaussian's footprint in depth order (0 past the kept ones)
-// and, when srect is given, the footprints themselves in depth order (empty
-// past the kept ones).
+// and, when srect is given, the binner boxes and group spans of the
+// footprints in depth order (empty past the kept ones).
 __global__ __launch_bounds__(kBlock) void k_gather_ntiles(const FrameDev* __restrict__ tab, BlockMap bm,
                                                           const uint32_t* __restrict__ counts,
                                                           const uint32_t* __restrict__ order,
                                                           const uint4* __restrict__ rect,
                                                           uint32_t* __restrict__ ntiles,
-                                                          uint4* __restrict__ srect)
+                                                          uint4* __restrict__ srect,
+                                                          uint32_t* __restrict__ sspan)
 {
     const int f = frame_of_block(bm, blockIdx.x);
     const FrameDev& F = tab[f];
@@ -363,7 +422,10 @@ __global__ __launch_bounds__(kBlock) void k_gather_ntiles(const FrameDev* __rest
         nt = Footprint(r).tiles();
     }
     ntiles[F.g0 + j] = nt;
-    if (srect) srect[F.g0 + j] = r;
+    if (srect) {
+        srect[F.g0 + j] = bin_box(r);
+        sspan[F.g0 + j] = group_span(r);
+    }
 }
 
 // Per-frame pair counts, arena slots (each frame's share rounded up to a whole
@@ -565,6 +627,24 @@ __device__ __forceinline__ uint32_t chunk_begin(uint32_t kept, uint32_t nch, uin
 // Boxes a counting-binner wave loads ahead of the one it is working on.
 constexpr int kBinAhead = 4;
 
+// Appends a counting-binner lane stages in LDS before the wave writes them
+// out, kStageDepth per tile.  A flush writes kStageTiles tiles per store, one
+// lane per staged append; rows of the stage are kStagePitch words apart, which
+// puts the 32 lanes of a half-wave in 32 different banks when a flush reads.
+constexpr uint32_t kStageDepth = 16;
+constexpr uint32_t kStageTiles = 64 / kStageDepth;
+constexpr uint32_t kStagePitch = 64 + 32 / kStageDepth;
+static_assert(kStageDepth * kStageTiles == 64 && kStageDepth <= 32, "a flush store covers whole tiles");
+constexpr uint32_t kFlushAhead = 2;  // flush stores whose stage reads are issued together
+
+// s_waitcnt operand that waits for the LDS/scalar-memory counter only
+// (lgkmcnt 0; vmcnt and expcnt at their maxima).
+constexpr int kWaitLgkm0 = 0xC07F;
+
+// Third word of a raw buffer resource on gfx9-class GPUs (32-bit data format,
+// no swizzle): range-checked loads at byte offsets below the record count.
+constexpr int kBufferWord3 = 0x00020000;
+
 // One block (256 lanes) per (frame, chunk) writes the chunk's row of the
 // count matrix (zeros for a frame whose pairs overflowed).  Per-row difference
 // array over the frame's tiles in LDS: a footprint whose row y spans tiles
@@ -587,8 +667,9 @@ __global__ __launch_bounds__(256) void k_tile_count(const FrameDev* __restrict__
     const uint32_t j0 = chunk_begin(kept, F.nch, c), j1 = chunk_begin(kept, F.nch, c + 1);
     if (live) {
         for (uint32_t j = j0 + threadIdx.x; j < j1; j += 256) {
-            const Footprint fp(srect[F.g0 + j]);
-            if (!fp.trimmed()) {
+            const uint4 bb = srect[F.g0 + j];
+            const Footprint fp(bb);
+            if (!is_mask_box(bb.x, bb.y) && !fp.trimmed()) {
                 for (uint32_t y = fp.y0; y < fp.y1; ++y) {
                     atomicAdd(&s_d[y * tx + fp.x0], 1u);
                     if (fp.x1 < tx) atomicSub(&s_d[y * tx + fp.x1], 1u);
@@ -597,7 +678,7 @@ __global__ __launch_bounds__(256) void k_tile_count(const FrameDev* __restrict__
             }
             for (uint32_t r = 0; r < fp.h(); ++r) {
                 int a, b;
-                fp.row(r, a, b);
+                bin_box_row(bb, r, a, b);
                 if (a >= b) continue;
                 const uint32_t y = fp.y0 + r;
                 atomicAdd(&s_d[y * tx + a], 1u);
@@ -623,87 +704,185 @@ __global__ __launch_bounds__(256) void k_tile_count(const FrameDev* __restrict__
 // runs of the group's tiles, starting at the slots the scans gave.  Logical
 // block b of a frame is chunk b / groups, group b % groups, and logical
 // blocks are laid out contiguously per XCD, so the groups of one chunk run
-// side by side on one XCD and share its boxes in that XCD's L2.
+// side by side on one XCD and share its group spans in that XCD's L2.
+//
+// The wave reads the chunk's 4-byte group spans, a set of kBinAhead * 64 at a
+// time; only the lanes whose entry meets the group fetch its footprint and
+// index.  Three sets are in flight: the spans of the next one or two, the
+// footprints of the current one, and the set being visited.  Each lane
+// stages its appends in LDS (kStageDepth per tile); when one lane's stage is
+// full, and at the end, the wave writes the staged runs out tile by tile with
+// all its lanes, so the arena receives contiguous runs rather than scattered
+// 4-byte stores.
 __global__ __launch_bounds__(64) void k_group_place(const FrameDev* __restrict__ tab, BlockMap cm,
                                                     const uint32_t* __restrict__ counts,
                                                     const uint32_t* __restrict__ order,
                                                     const uint4* __restrict__ srect,
+                                                    const uint32_t* __restrict__ sspan,
                                                     const uint32_t* __restrict__ cnt_pre,
                                                     const uint32_t* __restrict__ tstart,
                                                     uint32_t* __restrict__ pair_g)
 {
+    constexpr uint32_t kSet = kBinAhead * 64;
     const uint32_t lb = xcd_contiguous(blockIdx.x, gridDim.x);
     const int f = frame_of_block(cm, lb);
-    const FrameDev& F = tab[f];
     const uint32_t b = lb - cm.start[f];
+    const FrameDev& F = tab[f];
     const uint32_t tx = F.tiles_x, ty = F.tiles_y, T = tx * ty;
     const uint32_t gxn = (tx + kGroup - 1) / kGroup;
     const uint32_t ngr = gxn * ((ty + kGroup - 1) / kGroup);
     const uint32_t c = b / ngr, gr = b - c * ngr;
-    const uint32_t bx0 = (gr % gxn) * kGroup, by0 = (gr / gxn) * kGroup;
+    const uint32_t gx = gr % gxn, gy = gr / gxn;
     const uint32_t lane = threadIdx.x;
-    const uint32_t lx = bx0 + (lane % kGroup), ly = by0 + (lane / kGroup);
+    const uint32_t lx = gx * kGroup + (lane % kGroup), ly = gy * kGroup + (lane / kGroup);
     const bool valid = lx < tx && ly < ty;
     const uint32_t t = ly * tx + lx;
     const uint32_t* cf = counts + f * SD7_CNT_WORDS;
     const uint32_t kept = cf[SD7_CNT_KEPT];
     const uint32_t j0 = chunk_begin(kept, F.nch, c), j1 = chunk_begin(kept, F.nch, c + 1);
     if (cf[SD7_CNT_PAIRS] == 0 || j0 >= j1) return;  // uniform over the wave
-    uint32_t slot = 0;  // next arena slot of the lane's tile
+    __shared__ uint32_t s_stage[kStageDepth * kStagePitch];  // [depth][lane]
+    // LDS pointers (address space 3), so the stage is written with LDS stores
+    using lds_u32 = __attribute__((address_space(3))) uint32_t;
+    lds_u32* const s_lane = (lds_u32*)(s_stage + lane);  // the lane's column
+    lds_u32* const s_end = s_lane + kStageDepth * kStagePitch;
+    lds_u32* sp = s_lane;  // next free row of the lane's column
+    uint32_t slot = 0;      // arena slot of the lane's first staged append
     {
         const uint32_t* ts = tstart + F.t0;
         if (valid) slot = cf[SD7_CNT_PAIR_BASE] + (ts[t] - ts[0]) + cnt_pre[F.m0 + (size_t)c * T + t];
     }
     const uint4* rf = srect + F.g0;
     const uint32_t* of = order + F.g0;
-    // Visit the footprints of entries jb + k * 64 + lane (k < kBinAhead) that
-    // meet the group, in depth order; entries past j1 (loaded in bounds from
-    // j1 - 1) take no part.
-    auto visit = [&](const uint4 (&r)[kBinAhead], const uint32_t (&g)[kBinAhead], uint32_t jb) {
+    const uint32_t* sf = sspan + F.g0;
+    // spans of entries jb + k * 64 + lane, loaded in bounds (from j1 - 1 past the chunk)
+    auto load_spans = [&](uint32_t (&d)[kBinAhead], uint32_t jb) {
+#pragma unroll
+        for (int k = 0; k < kBinAhead; ++k) d[k] = gload(sf, min(jb + k * 64 + lane, j1 - 1));
+    };
+    // Lanes of the set whose entry (inside the chunk) meets the group, and
+    // their footprints and Gaussian indices.  Every lane issues the two loads
+    // through a buffer resource of the set's 64 entries; the other lanes'
+    // offsets lie past its range, so they read nothing from memory, and the
+    // loads stay unconditional for the compiler's load-counter waits.
+    auto pick = [&](const uint32_t (&d)[kBinAhead], uint64_t (&m)[kBinAhead], uint4 (&r)[kBinAhead],
+                    uint32_t (&g)[kBinAhead], uint32_t jb) {
 #pragma unroll
         for (int k = 0; k < kBinAhead; ++k) {
-            const uint32_t x0 = r[k].x & 0xFFFFu, y0 = r[k].x >> 16;
-            const uint32_t x1 = r[k].y & 0xFFFFu, y1 = r[k].y >> 16;
-            const bool meets = (jb + k * 64 + lane < j1) & (x0 < bx0 + kGroup) & (x1 > bx0) &
-                               (y0 < by0 + kGroup) & (y1 > by0);
-            uint64_t m = __ballot(meets);
-            while (m) {  // the meeting boxes in depth order
-                const int p = __builtin_ctzll(m);
-                m &= m - 1;
-                const Footprint fp(make_uint4(__builtin_amdgcn_readlane(r[k].x, p),
-                                              __builtin_amdgcn_readlane(r[k].y, p),
-                                              __builtin_amdgcn_readlane(r[k].z, p),
-                                              __builtin_amdgcn_readlane(r[k].w, p)));
+            const uint32_t base = __builtin_amdgcn_readfirstlane(jb + k * 64);
+            const uint32_t nv = j1 > base ? j1 - base : 0u;
+            const uint64_t in_chunk = nv >= 64 ? ~0ull : (1ull << nv) - 1ull;
+            m[k] = __ballot(span_meets(d[k], gx, gy)) & in_chunk;
+            const bool mine = (m[k] >> lane) & 1ull;
+            const __amdgpu_buffer_rsrc_t br =
+                __builtin_amdgcn_make_buffer_rsrc((void*)(rf + base), 0, 64 * 16, kBufferWord3);
+            const __amdgpu_buffer_rsrc_t bo =
+                __builtin_amdgcn_make_buffer_rsrc((void*)(of + base), 0, 64 * 4, kBufferWord3);
+            const auto v = __builtin_amdgcn_raw_buffer_load_b128(br, mine ? lane * 16u : 64u * 16u, 0, 0);
+            r[k] = make_uint4(v[0], v[1], v[2], v[3]);
+            g[k] = __builtin_amdgcn_raw_buffer_load_b32(bo, mine ? lane * 4u : 64u * 4u, 0, 0);
+        }
+    };
+    // Write the staged appends of every lane to its run, kStageTiles tiles
+    // per store (lane = tile q + lane / kStageDepth, append lane % kStageDepth),
+    // the stage reads of kFlushAhead stores ahead of their stores.  The flush ends
+    // with every LDS operation complete (s_waitcnt lgkmcnt(0)), so the visit
+    // loop that resumes waits for none of them.
+    auto flush = [&]() {
+        const uint32_t nst = (uint32_t)(sp - s_lane) / kStagePitch;
+        const uint32_t i = lane % kStageDepth;
+        for (uint32_t q0 = 0; q0 < 64; q0 += kFlushAhead * kStageTiles) {
+            uint32_t n[kFlushAhead], s0[kFlushAhead], v[kFlushAhead];
+#pragma unroll
+            for (int u = 0; u < kFlushAhead; ++u) {
+                const uint32_t q = q0 + u * kStageTiles + lane / kStageDepth;
+                n[u] = __shfl(nst, (int)q);
+                s0[u] = __shfl(slot, (int)q);
+                v[u] = s_stage[i * kStagePitch + q];
+            }
+#pragma unroll
+            for (int u = 0; u < kFlushAhead; ++u)
+                if (i < n[u]) pair_g[s0[u] + i] = v[u];
+        }
+        slot += nst;
+        sp = s_lane;
+        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+    };
+    // The last flush: with few appends per tile, one store per stage row
+    // (each lane its own tile) takes fewer stores than one per kStageTiles
+    // tiles.
+    auto flush_last = [&]() {
+        const uint32_t nst = (uint32_t)(sp - s_lane) / kStagePitch;
+        uint32_t top = 0;  // most appends any lane holds
+#pragma unroll
+        for (uint32_t bit = kStageDepth; bit; bit >>= 1)
+            if (__ballot(nst >= top + bit)) top += bit;
+        if (top > kStageDepth / 2) {
+            flush();
+            return;
+        }
+        for (uint32_t r = 0; r < top; ++r)
+            if (r < nst) pair_g[slot + r] = s_lane[r * kStagePitch];
+    };
+    // the picked entries in depth order, one at a time
+    auto visit = [&](const uint64_t (&m)[kBinAhead], const uint4 (&r)[kBinAhead], const uint32_t (&g)[kBinAhead]) {
+#pragma unroll
+        for (int k = 0; k < kBinAhead; ++k) {
+            uint64_t mm = m[k];
+            while (mm) {
+                const int p = __builtin_ctzll(mm);
+                mm &= mm - 1;
+                const uint4 bb = make_uint4(__builtin_amdgcn_readlane(r[k].x, p), __builtin_amdgcn_readlane(r[k].y, p),
+                                            __builtin_amdgcn_readlane(r[k].z, p), __builtin_amdgcn_readlane(r[k].w, p));
                 const uint32_t gp = __builtin_amdgcn_readlane(g[k], p);
-                const uint32_t row = ly - fp.y0;  // wraps above the box
-                int a = (int)fp.x0, b = (int)fp.x1;
-                if (fp.trimmed()) fp.row(row, a, b);  // uniform branch
-                const bool hit = valid && row < fp.h() && (int)lx >= a && (int)lx < b;
-                if (hit) pair_g[slot++] = gp;
+                const uint32_t dx = lx - (bb.x & 0xFFFFu), dy = ly - (bb.x >> 16);  // wrap left of / above the box
+                bool hit;
+                if (is_mask_box(bb.x, bb.y)) {  // uniform branch
+                    const uint64_t mask = (uint64_t)bb.w << 32 | bb.z;
+                    hit = (dx < kMaskSide) & (dy < kMaskSide) & (((mask >> ((dy * kMaskSide + dx) & 63u)) & 1u) != 0);
+                } else {
+                    const Footprint fp(bb);
+                    int a = (int)fp.x0, e = (int)fp.x1;
+                    if (fp.trimmed()) fp.row(dy, a, e);  // uniform branch
+                    hit = valid & (dy < fp.h()) & ((int)lx >= a) & ((int)lx < e);
+                }
+                if (hit) {
+                    *sp = gp;
+                    sp += kStagePitch;
+                }
+                if (__ballot(sp == s_end)) flush();
             }
         }
     };
-    auto load = [&](uint4 (&r)[kBinAhead], uint32_t (&g)[kBinAhead], uint32_t jb) {
-#pragma unroll
-        for (int k = 0; k < kBinAhead; ++k) {
-            const uint32_t jj = min(jb + k * 64 + lane, j1 - 1);
-            r[k] = rf[jj];
-            g[k] = of[jj];
-        }
-    };
-    // Two sets of footprints in flight: one is visited while the next one
-    // loads, alternating without register copies.
+    uint32_t da[kBinAhead], db[kBinAhead];
+    uint64_t ma[kBinAhead], mb[kBinAhead];
     uint4 ra[kBinAhead], rb[kBinAhead];
     uint32_t ga[kBinAhead], gb[kBinAhead];
-    load(ra, ga, j0);
-    for (uint32_t j = j0; j < j1; j += 2 * kBinAhead * 64) {
-        const uint32_t jn = j + kBinAhead * 64;
-        load(rb, gb, jn);
-        visit(ra, ga, j);
-        if (jn >= j1) break;
-        load(ra, ga, jn + kBinAhead * 64);
-        visit(rb, gb, jn);
+    // The scheduling barriers keep the loads in the order written, so that
+    // the compiler's load-counter waits leave the later sets in flight.
+    load_spans(da, j0);
+    load_spans(db, j0 + kSet);
+    __builtin_amdgcn_sched_barrier(0);
+    pick(da, ma, ra, ga, j0);
+    __builtin_amdgcn_sched_barrier(0);
+    load_spans(da, j0 + 2 * kSet);
+    __builtin_amdgcn_sched_barrier(0);
+    // Sets alternate between the a and b registers without copies.  The loop
+    // has no exit in the middle (a set past the chunk picks nothing), for the
+    // same reason.
+    for (uint32_t j = j0; j < j1; j += 2 * kSet) {
+        pick(db, mb, rb, gb, j + kSet);
+        __builtin_amdgcn_sched_barrier(0);
+        load_spans(db, j + 3 * kSet);
+        __builtin_amdgcn_sched_barrier(0);
+        visit(ma, ra, ga);
+        pick(da, ma, ra, ga, j + 2 * kSet);
+        __builtin_amdgcn_sched_barrier(0);
+        load_spans(da, j + 4 * kSet);
+        __builtin_amdgcn_sched_barrier(0);
+        visit(mb, rb, gb);
     }
+    flush_last();
 }
 
 // Per tile, exclusive prefix over the chunks (in place) and the tile's total.
