@@ -624,8 +624,8 @@ __device__ __forceinline__ uint32_t chunk_begin(uint32_t kept, uint32_t nch, uin
     return min(kept, c * len);
 }
 
-// Boxes a counting-binner wave loads ahead of the one it is working on.
-constexpr int kBinAhead = 4;
+// Entries of one placement pipeline stage, in units of 64 (one per lane).
+constexpr int kBinAhead = 1;
 
 // Appends a counting-binner lane stages in LDS before the wave writes them
 // out, kStageDepth per tile.  A flush writes kStageTiles tiles per store, one
