@@ -217,10 +217,12 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__
     }
 }
 
-// Stable scatter.  Wave w of a work tile owns elements [w*1024, (w+1)*1024)
-// of the tile and ranks them in 16 rounds of 64 (wave-level multisplit: eight
-// ballots find the lanes that share a digit); the per-wave digit counts are
-// then scanned across waves.
+// Stable scatter.  Wave w of a work tile owns elements [w*512, (w+1)*512)
+// of the tile and ranks them in kSortPerThread rounds of 64 (wave-level
+// multisplit: eight ballots find the lanes that share a digit); the per-wave
+// digit counts are then scanned across waves and over the digits.  The tile's
+// elements are placed in digit order in LDS and written out from there, so
+// each store covers whole runs of one digit rather than one element per run.
 template <bool FIRST>
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ keys_in,
                                                        const uint32_t* __restrict__ vals_in,
@@ -232,6 +234,9 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
 {
     __shared__ uint32_t s_goff[256];
     __shared__ uint32_t s_wh[4][256];
+    __shared__ uint32_t s_dst[256];  // first position of each digit in the tile (digit order)
+    __shared__ uint32_t s_tmp[4];
+    __shared__ uint32_t s_key[kSortItems], s_val[kSortItems];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t lt = lanemask_lt();
     const uint32_t nwt = tot->wt;
@@ -270,24 +275,47 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
             okmask |= (ok ? 1u : 0u) << r;
         }
         __syncthreads();
-        {
-            uint32_t run = 0;
+        uint32_t run = 0;  // the tile's count of digit tid
 #pragma unroll
-            for (int w2 = 0; w2 < 4; ++w2) {
-                const uint32_t t = s_wh[w2][tid];
-                s_wh[w2][tid] = run;
-                run += t;
+        for (int w2 = 0; w2 < 4; ++w2) {
+            const uint32_t t = s_wh[w2][tid];
+            s_wh[w2][tid] = run;
+            run += t;
+        }
+        // exclusive scan of the digit counts over the 256 digits
+        {
+            uint32_t v = run;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t t = __shfl_up(v, off);
+                if (lane >= off) v += t;
             }
+            if (lane == 63) s_tmp[wave] = v;
+            __syncthreads();
+            uint32_t before = 0;
+#pragma unroll
+            for (int w2 = 0; w2 < 4; ++w2)
+                if (w2 < wave) before += s_tmp[w2];
+            s_dst[tid] = before + v - run;
         }
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < kSortPerThread; ++r) {
             if ((okmask >> r) & 1u) {
                 const uint32_t d = (key[r] >> shift) & 255u;
-                const uint32_t p = s_goff[d] + s_wh[wave][d] + rank[r];
-                keys_out[p] = key[r];
-                vals_out[p] = val[r];
+                const uint32_t q = s_dst[d] + s_wh[wave][d] + rank[r];
+                s_key[q] = key[r];
+                s_val[q] = val[r];
             }
+        }
+        __syncthreads();
+        const uint32_t ntile = s_tmp[0] + s_tmp[1] + s_tmp[2] + s_tmp[3];  // elements the tile keeps
+        for (uint32_t q = tid; q < ntile; q += 256) {
+            const uint32_t kk = s_key[q];
+            const uint32_t d = (kk >> shift) & 255u;
+            const uint32_t p = s_goff[d] + (q - s_dst[d]);
+            keys_out[p] = kk;
+            vals_out[p] = s_val[q];
         }
         __syncthreads();
     }
