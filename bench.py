@@ -186,9 +186,32 @@ def run_steps(R, batches, steps, streams, record_stage=None):
     return dt, [e0.elapsed_time(e1) for e0, e1 in ev]
 
 
-def stage_hbm_fracs(stage_ms, n, views, batch, kept, pairs, tiles):
+def copy_bandwidth(mib: int = 1024, reps: int = 10):
+    """HBM bandwidth a plain device-to-device copy reaches (bytes read +
+    written per second, the mean of `reps` timed copies of `mib` MiB after one
+    untimed one): the practical ceiling beside the 8 TB/s peak."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    return {"gb_s": round(2 * n * 4 / t / 1e9, 1), "bytes_per_copy": 2 * n * 4,
+            "kind": f"device copy of {mib} MiB (torch copy_), mean of {reps}"}
+
+
+def stage_hbm_fracs(stage_ms, n, views, batch, kept, pairs, tiles, copy_gb_s=None):
     """Algorithmic HBM bytes of a step's slice + project and binning stages and
-    the fraction of the 8 TB/s peak their serial times reach.  Slice + project:
+    the fraction of the 8 TB/s peak their serial times reach (and of the
+    measured copy bandwidth when given).  Slice + project:
     the 336 B of scene parameters read once per run of up to 16 frames sharing
     the scene, and per (Gaussian, frame) the 108 B written (sliced mean,
     covariance and opacity 40 B, splat record 48 B, footprint 16 B, depth key
@@ -202,6 +225,8 @@ def stage_hbm_fracs(stage_ms, n, views, batch, kept, pairs, tiles):
         t = stage_ms[name] * 1e-3
         out[name] = {"algorithmic_bytes": int(b), "gb_s": round(b / t / 1e9, 1),
                      "frac": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}
+        if copy_gb_s:
+            out[name]["frac_of_copy"] = round(b / t / 1e9 / copy_gb_s, 4)
     return out
 
 
@@ -320,8 +345,9 @@ def main():
         R.stage("sd7_render", bc)
         contribs += sum(int(fr.ncontrib.to(torch.int64).sum()) for fr in fc)
     per_step_stage = serial_stage_ms(R, batches, 2)
+    hbm_copy = copy_bandwidth()
     stage_hbm = stage_hbm_fracs(per_step_stage, scene.n, len(views), a.batch, sum(kept), sum(pairs),
-                                len(views) * ((W + 15) // 16) * ((H + 15) // 16))
+                                len(views) * ((W + 15) // 16) * ((H + 15) // 16), hbm_copy["gb_s"])
 
     # -- roofline of the dominant kernel (the rasterizer): its launches in the
     # timed region, HIP events on their own stream (other batches' stages run
@@ -397,6 +423,7 @@ def main():
         "pairs_per_view_mean": int(np.mean(pairs)), "kept_per_view_mean": int(np.mean(kept)),
         "overflowed_frames": overflow,
         "stage_hbm": stage_hbm,
+        "hbm_copy": hbm_copy,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "serving": serving,

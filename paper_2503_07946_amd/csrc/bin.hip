@@ -371,37 +371,35 @@ __global__ __launch_bounds__(64) void k_setup_depth(const FrameDev* __restrict__
 }
 
 // The counting binner's copy of a footprint.  A box of at most kMaskSide x
-// kMaskSide tiles keeps its covered tiles as a bit mask in z (rows 0..3) and w
-// (rows 4..7), bit 8 * row + column; a larger box keeps the row trims of its
-// footprint.  x and y (the box) are as in the footprint.
+// kMaskSide tiles carries kMaskFlag in x and its covered tiles as a bit mask
+// in z (rows 0..3) and w (rows 4..7), bit 8 * row + column; a larger box is
+// the footprint itself (row trims in z and w).  x = x0 | y0 << 16 and
+// y = x1 | y1 << 16 otherwise, as in the footprint (x0 < 1024, so bit 15 of
+// x is free for the flag).
 constexpr uint32_t kMaskSide = 8;
-
-__device__ __forceinline__ bool is_mask_box(uint32_t x, uint32_t y)
-{
-    return (y & 0xFFFFu) - (x & 0xFFFFu) <= kMaskSide && (y >> 16) - (x >> 16) <= kMaskSide;
-}
+constexpr uint32_t kMaskFlag = 0x8000u;
 
 __device__ __forceinline__ uint4 bin_box(uint4 f)
 {
-    if (!is_mask_box(f.x, f.y)) return f;
     const Footprint fp(f);
+    if (fp.w() > kMaskSide || fp.h() > kMaskSide) return f;
     uint64_t m = 0;
     for (uint32_t r = 0; r < fp.h(); ++r) {
         int a, b;
         fp.row(r, a, b);
         if (a < b) m |= (((1ull << (b - a)) - 1ull) << (a - (int)fp.x0)) << (kMaskSide * r);
     }
-    return make_uint4(f.x, f.y, (uint32_t)m, (uint32_t)(m >> 32));
+    return make_uint4(f.x | kMaskFlag, f.y, (uint32_t)m, (uint32_t)(m >> 32));
 }
 
 // Tile columns [a, b) of row r (0 <= r < h) of a binner box; empty when a >= b.
 __device__ __forceinline__ void bin_box_row(uint4 bb, uint32_t r, int& a, int& b)
 {
-    if (!is_mask_box(bb.x, bb.y)) {
+    if (!(bb.x & kMaskFlag)) {
         Footprint(bb).row(r, a, b);
         return;
     }
-    const int x0 = (int)(bb.x & 0xFFFFu);
+    const int x0 = (int)(bb.x & 0x7FFFu);
     const uint32_t bits = ((r < 4 ? bb.z : bb.w) >> (8 * (r & 3u))) & 0xFFu;
     a = x0 + (int)__builtin_ctz(bits | 0x100u);
     b = x0 + 32 - (int)__builtin_clz(bits | 1u);
@@ -696,8 +694,8 @@ __global__ __launch_bounds__(256) void k_tile_count(const FrameDev* __restrict__
     if (live) {
         for (uint32_t j = j0 + threadIdx.x; j < j1; j += 256) {
             const uint4 bb = srect[F.g0 + j];
-            const Footprint fp(bb);
-            if (!is_mask_box(bb.x, bb.y) && !fp.trimmed()) {
+            const Footprint fp(make_uint4(bb.x & ~kMaskFlag, bb.y, bb.z, bb.w));
+            if (!(bb.x & kMaskFlag) && !fp.trimmed()) {
                 for (uint32_t y = fp.y0; y < fp.y1; ++y) {
                     atomicAdd(&s_d[y * tx + fp.x0], 1u);
                     if (fp.x1 < tx) atomicSub(&s_d[y * tx + fp.x1], 1u);
@@ -860,16 +858,16 @@ __global__ __launch_bounds__(64) void k_group_place(const FrameDev* __restrict__
             while (mm) {
                 const int p = __builtin_ctzll(mm);
                 mm &= mm - 1;
-                const uint4 bb = make_uint4(__builtin_amdgcn_readlane(r[k].x, p), __builtin_amdgcn_readlane(r[k].y, p),
-                                            __builtin_amdgcn_readlane(r[k].z, p), __builtin_amdgcn_readlane(r[k].w, p));
+                const uint32_t bx = __builtin_amdgcn_readlane(r[k].x, p);
+                const uint32_t bz = __builtin_amdgcn_readlane(r[k].z, p), bw = __builtin_amdgcn_readlane(r[k].w, p);
                 const uint32_t gp = __builtin_amdgcn_readlane(g[k], p);
-                const uint32_t dx = lx - (bb.x & 0xFFFFu), dy = ly - (bb.x >> 16);  // wrap left of / above the box
+                const uint32_t dx = lx - (bx & 0x7FFFu), dy = ly - (bx >> 16);  // wrap left of / above the box
                 bool hit;
-                if (is_mask_box(bb.x, bb.y)) {  // uniform branch
-                    const uint64_t mask = (uint64_t)bb.w << 32 | bb.z;
-                    hit = (dx < kMaskSide) & (dy < kMaskSide) & (((mask >> ((dy * kMaskSide + dx) & 63u)) & 1u) != 0);
+                if (bx & kMaskFlag) {  // uniform branch
+                    const uint64_t mask = (uint64_t)bw << 32 | bz;
+                    hit = ((dx | dy) < kMaskSide) & (((mask >> ((dy * kMaskSide + dx) & 63u)) & 1u) != 0);
                 } else {
-                    const Footprint fp(bb);
+                    const Footprint fp(make_uint4(bx, __builtin_amdgcn_readlane(r[k].y, p), bz, bw));
                     int a = (int)fp.x0, e = (int)fp.x1;
                     if (fp.trimmed()) fp.row(dy, a, e);  // uniform branch
                     hit = valid & (dy < fp.h()) & ((int)lx >= a) & ((int)lx < e);
