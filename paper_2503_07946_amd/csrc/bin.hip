@@ -631,10 +631,11 @@ __global__ __launch_bounds__(256) void k_ranges(const FrameDev* __restrict__ tab
 // scan of the tile totals give every (chunk, tile) run its first arena slot,
 // so the runs of one tile follow each other in depth order.  k_group_place
 // then runs one wave per (chunk, group of 8 x 8 tiles), one lane per tile: it
-// scans the chunk's boxes in depth order, visits those that meet the group
-// one at a time, and every lane whose tile the Gaussian's footprint holds
-// appends the Gaussian to its run.  Each tile list thus comes out in (depth, index) order
-// without a sort over pairs, and every wave writes only its own 64 runs.
+// scans the 4-byte group spans of the chunk's boxes in depth order, fetches
+// the boxes that meet the group, visits them one at a time, and every lane
+// whose tile the box covers appends the Gaussian to its run (staged in LDS,
+// written out as runs).  Each tile list thus comes out in (depth, index)
+// order without a sort over pairs, and every wave writes only its own 64 runs.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ uint32_t frame_kept(const uint32_t* counts, int f)
@@ -733,13 +734,14 @@ __global__ __launch_bounds__(256) void k_tile_count(const FrameDev* __restrict__
 // side by side on one XCD and share its group spans in that XCD's L2.
 //
 // The wave reads the chunk's 4-byte group spans, a set of kBinAhead * 64 at a
-// time; only the lanes whose entry meets the group fetch its footprint and
-// index.  Three sets are in flight: the spans of the next one or two, the
-// footprints of the current one, and the set being visited.  Each lane
+// time; only the lanes whose entry meets the group fetch its binner box and
+// Gaussian index.  Three sets are in flight: the spans of the next one or
+// two, the boxes of the current one, and the set being visited.  Each lane
 // stages its appends in LDS (kStageDepth per tile); when one lane's stage is
-// full, and at the end, the wave writes the staged runs out tile by tile with
-// all its lanes, so the arena receives contiguous runs rather than scattered
-// 4-byte stores.
+// full, and at the end, the wave writes the staged runs out with all its
+// lanes, kStageTiles tiles per store (the last flush, when no tile holds
+// more than half a stage, one stage row per store), so the arena receives
+// runs rather than scattered 4-byte stores.
 __global__ __launch_bounds__(64) void k_group_place(const FrameDev* __restrict__ tab, BlockMap cm,
                                                     const uint32_t* __restrict__ counts,
                                                     const uint32_t* __restrict__ order,
@@ -767,7 +769,7 @@ __global__ __launch_bounds__(64) void k_group_place(const FrameDev* __restrict__
     const uint32_t kept = cf[SD7_CNT_KEPT];
     const uint32_t j0 = chunk_begin(kept, F.nch, c), j1 = chunk_begin(kept, F.nch, c + 1);
     if (cf[SD7_CNT_PAIRS] == 0 || j0 >= j1) return;  // uniform over the wave
-    __shared__ uint32_t s_stage[kStageDepth * kStagePitch];  // [depth][lane]
+    __shared__ uint32_t s_stage[(kStageDepth + 1) * kStagePitch];  // [depth][lane], and a spare row
     // LDS pointers (address space 3), so the stage is written with LDS stores
     using lds_u32 = __attribute__((address_space(3))) uint32_t;
     lds_u32* const s_lane = (lds_u32*)(s_stage + lane);  // the lane's column
@@ -857,25 +859,24 @@ __global__ __launch_bounds__(64) void k_group_place(const FrameDev* __restrict__
             uint64_t mm = m[k];
             while (mm) {
                 const int p = __builtin_ctzll(mm);
-                mm &= mm - 1;
+                mm ^= 1ull << p;
                 const uint32_t bx = __builtin_amdgcn_readlane(r[k].x, p);
                 const uint32_t bz = __builtin_amdgcn_readlane(r[k].z, p), bw = __builtin_amdgcn_readlane(r[k].w, p);
                 const uint32_t gp = __builtin_amdgcn_readlane(g[k], p);
                 const uint32_t dx = lx - (bx & 0x7FFFu), dy = ly - (bx >> 16);  // wrap left of / above the box
-                bool hit;
-                if (bx & kMaskFlag) {  // uniform branch
-                    const uint64_t mask = (uint64_t)bw << 32 | bz;
-                    hit = ((dx | dy) < kMaskSide) & (((mask >> ((dy * kMaskSide + dx) & 63u)) & 1u) != 0);
-                } else {
+                // the coverage-mask test, replaced below for a larger box
+                const uint64_t mask = (uint64_t)bw << 32 | bz;
+                bool hit = ((dx | dy) < kMaskSide) & (((mask >> ((dy * kMaskSide + dx) & 63u)) & 1u) != 0);
+                if (!(bx & kMaskFlag)) {  // uniform branch
                     const Footprint fp(make_uint4(bx, __builtin_amdgcn_readlane(r[k].y, p), bz, bw));
-                    int a = (int)fp.x0, e = (int)fp.x1;
-                    if (fp.trimmed()) fp.row(dy, a, e);  // uniform branch
+                    int a, e;
+                    fp.row(dy, a, e);
                     hit = valid & (dy < fp.h()) & ((int)lx >= a) & ((int)lx < e);
                 }
-                if (hit) {
-                    *sp = gp;
-                    sp += kStagePitch;
-                }
+                // every lane writes: a lane without a hit writes to the spare
+                // row past its column's last, and its pointer stays
+                *(hit ? sp : s_end) = gp;
+                sp += hit ? kStagePitch : 0u;
                 if (__ballot(sp == s_end)) flush();
             }
         }
