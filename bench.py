@@ -97,6 +97,9 @@ def parse():
     ap.add_argument("--serve-qps", type=float, default=0.0, help="0: 0.9x the plain path's capacity")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--serve-sizes", type=str, default="100000,300000,1000000,2000000")
+    ap.add_argument("--train", type=int, default=1,
+                    help="also time the training step (forward, L1 gradient, reverse pass, Adam) on 500k Gaussians at 1352x1014")
+    ap.add_argument("--train-steps", type=int, default=10)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -249,6 +252,83 @@ def serial_stage_ms(R, batches, reps):
             for k, s in enumerate(names):
                 ms[s].append(e[k].elapsed_time(e[k + 1]))
     return {s: round(float(np.mean(v)) * len(batches), 4) for s, v in ms.items()}
+
+
+def train_bench(a, R, L):
+    """The reverse pass in a training step (scenegen.config2: 500,000 Gaussians,
+    one 1352x1014 view and its seeded target): per step the forward stages, the
+    L1 loss gradient image, the three reverse stages and the Adam update, on one
+    stream, each bracketed by HIP events; `train_steps` timed steps after two
+    untimed ones."""
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_2503_07946_amd.render import Adam, GaussianScene
+
+    scene, views, target = scenegen.config2()
+    v = views[0]
+    gs = GaussianScene.from_host(scene)
+    tgt = torch.as_tensor(target, device="cuda")
+    c0 = R.read_counts(R.render(gs, v))
+    cap = int(int(c0[0, L.SD7_CNT_NEEDED]) * 1.5) + L.SD7_PAIR_ROUND  # room for the pairs to grow as it trains
+    frames = R.make_frames([(gs, v)], need_grad=True)
+    fr = frames[0]
+    fr.dL_dimage = torch.empty_like(fr.image)
+    fr.grads["lambda"] = torch.zeros(2, dtype=torch.float32, device="cuda")
+    b = R.batch(frames, cap)
+    opt = Adam(gs)
+    st = torch.cuda.current_stream()
+    tmp = torch.empty_like(fr.image)
+    names = ("sd7_slice_project", "sd7_bin", "sd7_rasterize", "loss_gradient",
+             "sd7_rasterize_backward", "sd7_project_backward", "sd7_slice_backward", "adam")
+    inv = 1.0 / tgt.numel()
+
+    def step(ev):
+        k = 0
+        for name in names:
+            if name == "loss_gradient":  # d(mean |image - target|) / d image
+                torch.sub(fr.image, tgt, out=tmp)
+                torch.sign(tmp, out=fr.dL_dimage)
+                fr.dL_dimage.mul_(inv)
+                fr.grads["lambda"].zero_()
+            elif name == "adam":
+                opt.step(gs, fr.grads)
+            else:
+                R.stage(name, b, stream=st)
+            if ev is not None:
+                ev[k].record(st)
+            k += 1
+
+    for _ in range(2):
+        step(None)
+    runs = []
+    torch.cuda.synchronize()
+    for _ in range(a.train_steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in names]
+        e0.record(st)
+        step(ev)
+        runs.append((e0, ev))
+    torch.cuda.synchronize()
+    per = {n: [] for n in names}
+    total = []
+    for e0, ev in runs:
+        prev = e0
+        for n, e in zip(names, ev):
+            per[n].append(prev.elapsed_time(e))
+            prev = e
+        total.append(e0.elapsed_time(ev[-1]))
+    c = R.read_counts(b)
+    loss = float((fr.image - tgt).abs().mean())
+    stage_ms = {n: round(float(np.mean(x)), 4) for n, x in per.items()}
+    return {"workload": "500k 7D Gaussians, one 1352x1014 view, L1 loss against a seeded target, "
+                        "forward + reverse pass + Adam per step",
+            "ms_per_step": round(float(np.mean(total)), 4), "steps": a.train_steps,
+            "stage_ms": stage_ms,
+            "pairs": int(c[0, L.SD7_CNT_PAIRS]),
+            "overflowed": bool(c[0, L.SD7_CNT_FLAGS] & L.SD7_FLAG_PAIR_OVERFLOW),
+            "l1_loss_after": round(loss, 6)}
 
 
 def agr_bench(a, R, L, scene, views, streams):
@@ -406,6 +486,7 @@ def main():
 
     serving = serve_bench(a, R, L) if a.serve else None
     agr = agr_bench(a, R, L, scene, views, streams) if a.agr else None
+    training = train_bench(a, R, L) if a.train else None
 
     out = {
         "metric": "rendered FPS and Mpixel/s at 1 GPU; p50/p99 frame latency, batched vs plain",
@@ -428,6 +509,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "agr": agr,
+        "training": training,
     }
     print(json.dumps(out))
     return 0

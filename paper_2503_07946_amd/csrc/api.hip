@@ -761,9 +761,8 @@ sd7_status sd7_adam_step(sd7_ctx* ctx, int64_t n, const sd7_arrays* params, cons
     a.rsbc2 = (float)(1.0 / std::sqrt(1.0 - std::pow((double)cfg->beta2, cfg->step)));
     a.alpha_lo = cfg->alpha_lo; a.alpha_hi = cfg->alpha_hi; a.diag_min = cfg->diag_min;
     HIP_TRY(hipSetDevice(ctx->device));
-    const uint64_t total = 84ull * (uint64_t)n;
-    k_adam<<<(uint32_t)((total + kBlock - 1) / kBlock), kBlock, 0, static_cast<hipStream_t>(stream)>>>(
-        (uint32_t)n, P, G, M, V, a);
+    const uint32_t chunks = ceil_div((uint64_t)n, (uint64_t)kBlock * kAdamPerThread);
+    k_adam<<<84u * chunks, kBlock, 0, static_cast<hipStream_t>(stream)>>>((uint32_t)n, chunks, P, G, M, V, a);
     LAUNCH_CHECK("k_adam");
     return SD7_OK;
 }

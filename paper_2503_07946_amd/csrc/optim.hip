@@ -20,38 +20,58 @@ struct AdamArgs {
     float alpha_lo, alpha_hi, diag_min;
 };
 
-// One lane per parameter value; block b covers values [256 b, 256 b + 256)
-// of the 84 n values taken group by group.  Adam in the order PyTorch uses:
-// m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2;
+// Values of one parameter plane a k_adam thread updates (kBlock apart).
+constexpr uint32_t kAdamPerThread = 4;
+
+// Block b updates values [chunk * kBlock * kAdamPerThread, ...) of plane
+// b / chunks of the 84 per-Gaussian planes taken group by group (the group,
+// its learning rate and clamps are uniform over the block).  Adam in the
+// order PyTorch uses: m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2;
 // p -= (lr / (1 - b1^t)) m / (sqrt(v) / sqrt(1 - b2^t) + eps); then the
 // opacity is clamped to [alpha_lo, alpha_hi] and L's diagonal to >= diag_min.
-__global__ __launch_bounds__(kBlock) void k_adam(uint32_t n, ArraySet p, ArraySet g, ArraySet m, ArraySet v,
-                                                 AdamArgs c)
+__global__ __launch_bounds__(kBlock) void k_adam(uint32_t n, uint32_t chunks, ArraySet p, ArraySet g, ArraySet m,
+                                                 ArraySet v, AdamArgs c)
 {
-    const uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    uint64_t off = e;
+    const uint32_t plane = blockIdx.x / chunks, chunk = blockIdx.x - plane * chunks;
     int grp = 0;
+    uint32_t pl = plane;  // plane within the group
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        const uint64_t len = (uint64_t)kGroupPlanes[grp] * n;
-        if (off >= len) { off -= len; ++grp; }
+    for (int k = 0; k < 5; ++k)
+        if (pl >= (uint32_t)kGroupPlanes[grp]) { pl -= kGroupPlanes[grp]; ++grp; }
+    const size_t base = (size_t)pl * n;
+    float* __restrict__ pp = p.a[grp] + base;
+    const float* __restrict__ gg = g.a[grp] + base;
+    float* __restrict__ mp = m.a[grp] + base;
+    float* __restrict__ vp = v.a[grp] + base;
+    const float step = c.lr[grp] * c.rbc1;
+    const bool clamp_alpha = grp == 4;
+    const bool clamp_diag = grp == 3 && (pl == 0 || pl == 2 || pl == 5 || pl == 9 || pl == 14 || pl == 20 || pl == 27);
+    const uint32_t i0 = chunk * kBlock * kAdamPerThread + threadIdx.x;
+    float gr[kAdamPerThread], m0[kAdamPerThread], v0[kAdamPerThread], p0[kAdamPerThread];
+#pragma unroll
+    for (uint32_t k = 0; k < kAdamPerThread; ++k) {
+        const uint32_t i = i0 + k * kBlock;
+        if (i < n) {
+            gr[k] = gg[i];
+            m0[k] = mp[i];
+            v0[k] = vp[i];
+            p0[k] = pp[i];
+        }
     }
-    if (grp >= 6 || off >= (uint64_t)kGroupPlanes[grp] * n) return;
-    const float gr = g.a[grp][off];
-    const float mm = fmaf(c.beta1, m.a[grp][off], (1.0f - c.beta1) * gr);
-    const float vv = fmaf(c.beta2, v.a[grp][off], (1.0f - c.beta2) * gr * gr);
-    m.a[grp][off] = mm;
-    v.a[grp][off] = vv;
-    const float denom = sqrtf(vv) * c.rsbc2 + c.eps;
-    float x = p.a[grp][off] - (c.lr[grp] * c.rbc1) * (mm / denom);
-    if (grp == 4) x = fminf(fmaxf(x, c.alpha_lo), c.alpha_hi);
-    if (grp == 3) {
-        const uint32_t plane = (uint32_t)(off / n);
-        const bool diag = plane == 0 || plane == 2 || plane == 5 || plane == 9 || plane == 14 || plane == 20 ||
-                          plane == 27;
-        if (diag) x = fmaxf(x, c.diag_min);
+#pragma unroll
+    for (uint32_t k = 0; k < kAdamPerThread; ++k) {
+        const uint32_t i = i0 + k * kBlock;
+        if (i >= n) continue;
+        const float mm = fmaf(c.beta1, m0[k], (1.0f - c.beta1) * gr[k]);
+        const float vv = fmaf(c.beta2, v0[k], (1.0f - c.beta2) * gr[k] * gr[k]);
+        mp[i] = mm;
+        vp[i] = vv;
+        const float denom = sqrtf(vv) * c.rsbc2 + c.eps;
+        float x = p0[k] - step * (mm / denom);
+        if (clamp_alpha) x = fminf(fmaxf(x, c.alpha_lo), c.alpha_hi);
+        if (clamp_diag) x = fmaxf(x, c.diag_min);
+        pp[i] = x;
     }
-    p.a[grp][off] = x;
 }
 
 // keep[i] = alpha[i] >= tau, and the same flags into pos (scanned in place next)
