@@ -182,15 +182,28 @@ __device__ __forceinline__ float dpp_add(float v)
     return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, true));
 }
 
-__device__ __forceinline__ float wave_sum_to_lane63(float v)
+// Sums of N values over the wave, each left in lane 63 (the other lanes hold
+// partial sums); the N reductions go step by step together, so that each DPP
+// read finds its operand written several instructions earlier.
+template <int N>
+__device__ __forceinline__ void wave_sums_to_lane63(float (&v)[N])
 {
-    v = dpp_add<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
-    v = dpp_add<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
-    v = dpp_add<0x141, 0xF>(v);  // row_half_mirror
-    v = dpp_add<0x140, 0xF>(v);  // row_mirror: every lane of a row holds the row sum
-    v = dpp_add<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-    v = dpp_add<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
-    return v;
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = dpp_add<0xB1, 0xF>(v[q]);   // quad_perm [1,0,3,2]
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = dpp_add<0x4E, 0xF>(v[q]);   // quad_perm [2,3,0,1]
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = dpp_add<0x141, 0xF>(v[q]);  // row_half_mirror
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = dpp_add<0x140, 0xF>(v[q]);  // row_mirror: every lane of a row holds the row sum
+    // Row 3 then adds row 2's sum (row_bcast:15) and row 1's, which by then
+    // holds rows 0 and 1 (row_bcast:31).  Only lane 63 is read afterwards, so
+    // every row takes part (the other rows end with partial sums), which lets
+    // each step be one DPP add.
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = dpp_add<0x142, 0xF>(v[q]);  // row_bcast:15
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = dpp_add<0x143, 0xF>(v[q]);  // row_bcast:31
 }
 
 __device__ __forceinline__ uint32_t wave_max(uint32_t v)
@@ -271,7 +284,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const FrameDev* __restrict__ 
             acc[k][0] = fmaf(s.r, wc, acc[k][0]);
             acc[k][1] = fmaf(s.g, wc, acc[k][1]);
             acc[k][2] = fmaf(s.b, wc, acc[k][2]);
-            const float inv = 1.0f / (1.0f - alpha);
+            const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);  // 1 - alpha >= 0.01: the hardware reciprocal (1 ulp)
             const float dot_rgb = gC[k][0] * s.r + gC[k][1] * s.g + gC[k][2] * s.b;
             const float dot_s = gC[k][0] * (Co[k][0] - acc[k][0]) + gC[k][1] * (Co[k][1] - acc[k][1]) +
                                 gC[k][2] * (Co[k][2] - acc[k][2]);
@@ -298,14 +311,15 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const FrameDev* __restrict__ 
         v9[6] = Sr;
         v9[7] = Sg;
         v9[8] = Sb;
-        float mine = 0.f;
+        wave_sums_to_lane63(v9);
+        float sum = 0.f;  // lane q < 9: the sum of v9[q]
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-            const float t = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_to_lane63(v9[q])), 63));
-            if (lane == (uint32_t)q) mine = t;
+            const float t = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v9[q]), 63));
+            if (lane == (uint32_t)q) sum = t;
         }
-        if (lane == 5) mine *= exp2_fast(-s.lo);  // d alpha / d alpha_c = alpha / alpha_c
-        if (lane < 9) atomicAdd(&d_splat[9 * g0 + (size_t)lane * n + g], mine);
+        if (lane == 5) sum *= exp2_fast(-s.lo);  // d alpha / d alpha_c = alpha / alpha_c
+        if (lane < 9) atomicAdd(&d_splat[9 * g0 + (size_t)lane * n + g], sum);
     }
 }
 
