@@ -46,8 +46,8 @@ FP32_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 RASTER_OPS_PER_TEST = 12
 RASTER_OPS_PER_CONTRIBUTION = 12
 RASTER_SRC_DIR = "paper_2503_07946_amd/csrc"
-RASTER_SRC_SHA256 = "15dfb74bbf0bc8759339009d86d21658905e4075b25ae6c808dd9949e94cd8f1"
-RASTER_TRAFFIC_BYTES = 2344317237       # (988436 KiB x 2 + 312500 KiB) x 1024
+RASTER_SRC_SHA256 = "f44db6ffd19c24f8d323fcf11bc98a24817336664c84a6228c29c2e78c3a1371"
+RASTER_TRAFFIC_BYTES = 2343108928       # (987846 KiB x 2 + 312500 KiB) x 1024
 RASTER_VALU_INSTRUCTIONS = 1108255228   # SQ_INSTS_VALU per launch (wave64 instructions)
 
 
