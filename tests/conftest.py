@@ -23,16 +23,17 @@ def _oracle_built():
 
 @pytest.fixture
 def report(request):
-    """Append measured parity figures to gpurun_out/parity_report.jsonl (when
-    that directory exists) so runs on the GPU machine leave a record."""
+    """Print measured parity figures as JSON lines, and append them to the file
+    named by SD7_PARITY_REPORT when that variable is set."""
     import json
     import time
-    path = os.path.join(ROOT, "gpurun_out", "parity_report.jsonl")
+    path = os.environ.get("SD7_PARITY_REPORT")
 
     def _rep(kind, **kw):
         rec = {"test": request.node.nodeid, "kind": kind, "time": time.time(), **kw}
         print(json.dumps(rec, default=float), flush=True)
-        if os.path.isdir(os.path.dirname(path)):
+        if path:
+            os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
             with open(path, "a") as f:
                 f.write(json.dumps(rec, default=float) + "\n")
     return _rep
