@@ -215,15 +215,15 @@ def stage_hbm_fracs(stage_ms, n, views, batch, kept, pairs, tiles, copy_gb_s=Non
     """Algorithmic HBM bytes of a step's slice + project and binning stages and
     the fraction of the 8 TB/s peak their serial times reach (and of the
     measured copy bandwidth when given).  Slice + project:
-    the 336 B of scene parameters read once per run of up to 16 frames sharing
-    the scene, and per (Gaussian, frame) the 108 B written (sliced mean,
+    the 336 B of scene parameters read once per launch (a batch of frames
+    sharing the scene), and per (Gaussian, frame) the 108 B written (sliced mean,
     covariance and opacity 40 B, splat record 48 B, footprint 16 B, depth key
     4 B).  Binning: the depth sort's 64 B per kept Gaussian (four passes, each
     reading and writing a key and a value), 4 B per pair of the tile lists and
     8 B per tile range."""
-    runs = views // batch * -(-batch // 16) + (-(-(views % batch) // 16) if views % batch else 0)
+    launches = -(-views // batch)
     out = {}
-    for name, b in (("sd7_slice_project", 336 * n * runs + 108 * n * views),
+    for name, b in (("sd7_slice_project", 336 * n * launches + 108 * n * views),
                     ("sd7_bin", 64 * kept + 4 * pairs + 8 * tiles)):
         t = stage_ms[name] * 1e-3
         out[name] = {"algorithmic_bytes": int(b), "gb_s": round(b / t / 1e9, 1),

@@ -177,17 +177,21 @@ sd7_status make_plan(const sd7_frame* fr, int nf, int64_t cap, Plan& P, bool nee
             }
         }
         int q = 0;
+        uint64_t units = 0;
         for (int g = 0; g < ng; ++g) {
             P.sgrp.first[g] = (uint8_t)q;
-            P.sgrp.start[g] = P.sblocks;
+            P.sgrp.start[g] = (uint32_t)std::min<uint64_t>(units, UINT32_MAX);
             const int q0 = q;
             for (int f = 0; f < nf; ++f)
                 if (owner[f] == g) P.sgrp.frame[q++] = (uint8_t)f;
-            P.sblocks += ceil_div(fr[head[g]].scene.n, kBlock) * ceil_div(q - q0, kFramesPerLane);
+            units += (uint64_t)ceil_div(fr[head[g]].scene.n, kBlock) * (uint64_t)(q - q0);
         }
         P.sgrp.first[ng] = (uint8_t)q;
-        P.sgrp.start[ng] = P.sblocks;
+        P.sgrp.start[ng] = (uint32_t)std::min<uint64_t>(units, UINT32_MAX);
         P.sgrp.ng = ng;
+        // whole rounds of resident blocks, equal shares of the units
+        const uint64_t rounds = std::max<uint64_t>(1, units / ((uint64_t)kSliceResident * kSliceUnitsPerBlock));
+        P.sblocks = (uint32_t)std::min<uint64_t>(units, kSliceResident * rounds);
     }
     P.tmap.start[nf] = P.tblocks;
     P.cmap.start[nf] = P.cblocks;

@@ -88,10 +88,10 @@ __device__ __forceinline__ int frame_of_block(const BlockMap& bm, uint32_t b)
 }
 
 // Frames of a call grouped by scene (same parameter arrays): group g owns
-// frame[first[g]] .. frame[first[g + 1] - 1] and launch blocks start[g] ..
-// start[g + 1] - 1 (kernel argument): ceil(n / kBlock) runs of Gaussians
-// times ceil(frames / kFramesPerLane) frame chunks.
-constexpr uint32_t kFramesPerLane = 16;
+// frame[first[g]] .. frame[first[g + 1] - 1] and the work units start[g] ..
+// start[g + 1] - 1 (kernel argument).  A unit is one (block of kBlock
+// Gaussians, frame) of the group, numbered Gaussian block by Gaussian block
+// and, within one, frame by frame.
 struct SceneGroups {
     uint32_t start[SD7_MAX_FRAMES + 1];
     uint8_t first[SD7_MAX_FRAMES + 1];
@@ -99,7 +99,15 @@ struct SceneGroups {
     int ng;
 };
 
-__device__ __forceinline__ int group_of_block(const SceneGroups& sg, uint32_t b)
+// The fused slice/projection grid is a whole number of rounds of
+// kSliceResident blocks, the blocks that are resident on the chip at once
+// (three per CU, set by their 48 KiB of LDS, on 256 CUs), each taking an
+// equal share of the units, about kSliceUnitsPerBlock of them or more.  Every
+// block then does the same work and no round runs partly filled.
+constexpr uint32_t kSliceResident = 768;
+constexpr uint32_t kSliceUnitsPerBlock = 8;
+
+__device__ __forceinline__ int group_of_unit(const SceneGroups& sg, uint32_t b)
 {
     int lo = 0, hi = sg.ng - 1;
     while (lo < hi) {  // largest g with start[g] <= b

@@ -2,17 +2,18 @@
 // (Sec. 4.2 then Sec. 4.4).  The conditional covariance, chol(Sigma_QQ),
 // V = Sigma_PQ C^{-T} and chol(Sigma_DD) do not depend on the view (t, d):
 // one lane per Gaussian forms them once, in FP64 registers, and then walks
-// a run of at most kFramesPerLane of the group's frames, doing only the view-dependent
-// part of the slice (the residual r, mu_c = mu_p + V C^{-1} r, the
-// modulations) and the projection of each.  The scene's parameters are read
-// once per kFramesPerLane frames instead of once per frame, and the sliced
-// statistics go to projection in registers.  The block's SH coefficients are
-// staged in LDS once (48 x 256 floats) and read from there by every frame.
-// The blocks of one run of 256
-// Gaussians (one per frame chunk) are adjacent and laid out contiguously per
-// XCD, so their scene reads meet in one L2.  The arithmetic is that of
-// k_slice and k_project, so every output is bitwise the same as the two
-// separate kernels'.
+// a run of the group's frames, doing only the view-dependent part of the
+// slice (the residual r, mu_c = mu_p + V C^{-1} r, the modulations) and the
+// projection of each.  The scene's parameters are read once per run instead
+// of once per frame, and the sliced statistics go to projection in registers.
+// The block's SH coefficients are staged in LDS once per run (48 x 256
+// floats) and read from there by every frame.
+// Each block takes an equal, contiguous share of the units (Gaussian block,
+// frame), so a block's runs are the frames of one or a few Gaussian blocks;
+// consecutive shares are laid out contiguously per XCD, so the scene reads of
+// one Gaussian block split over two blocks meet in one L2.  The arithmetic is
+// that of k_slice and k_project, so every output is bitwise the same as the
+// two separate kernels'.
 #include "common.h"
 #include "gload.h"
 
@@ -31,66 +32,73 @@ __global__ __launch_bounds__(kBlock, 3) void k_slice_project(const FrameDev* __r
                                                           uint32_t* __restrict__ counts)
 {
     const uint32_t lb = xcd_contiguous(blockIdx.x, gridDim.x);
-    const int gi = group_of_block(sg, lb);
-    const FrameDev& F0 = tab[sg.frame[sg.first[gi]]];
-    const uint32_t n = F0.n;
-    const uint32_t nq = sg.first[gi + 1] - sg.first[gi];
-    const uint32_t nchunk = (nq + kFramesPerLane - 1) / kFramesPerLane;
-    const uint32_t b = lb - sg.start[gi];
-    const uint32_t chunk = b % nchunk;
-    const uint32_t i = (b / nchunk) * kBlock + threadIdx.x;
-    const bool valid = i < n;
-    SliceFixed S;
-    float mu_p[3] = {0.f, 0.f, 0.f}, mu_d[3] = {0.f, 0.f, 0.f}, cv32[6];
-    float mu_t = 0.f, alpha = 0.f;
-    bool cv_fin = false;
-    uint32_t flag0 = 0;
+    const uint32_t units = sg.start[sg.ng];
+    uint32_t u = (uint32_t)((uint64_t)lb * units / gridDim.x);
+    const uint32_t u_end = (uint32_t)((uint64_t)(lb + 1) * units / gridDim.x);
+    int gi = group_of_unit(sg, u);
     __shared__ float s_sh[48 * kBlock];
-    if (valid) {
-        // every load of the Gaussian is issued before the first LDS store
-        float sh[48];
-#pragma unroll
-        for (int j = 0; j < 48; ++j) sh[j] = gload(F0.sh, (size_t)j * n + i);
-        double L[28];
-        load_L(F0.L, n, i, L);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) mu_p[a] = gload(F0.mu_p, (size_t)a * n + i);
-        mu_t = gload(F0.mu_t, i);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) mu_d[k] = gload(F0.mu_d, (size_t)k * n + i);
-        alpha = gload(F0.alpha, i);
-#pragma unroll
-        for (int j = 0; j < 48; ++j) s_sh[j * kBlock + threadIdx.x] = sh[j];
-        // each lane reads back only what it wrote: no barrier needed
-        slice_fixed(L, S, flag0);
-        cv_fin = slice_cov(S, cv32);
-    }
-    // the group's frames split into nchunk runs of nearly equal length
-    const uint32_t q0 = sg.first[gi] + chunk * nq / nchunk;
-    const uint32_t q1 = sg.first[gi] + (chunk + 1) * nq / nchunk;
-    for (uint32_t q = q0; q < q1; ++q) {
-        const int f = sg.frame[q];
-        const FrameDev& F = tab[f];
-        uint32_t flag = flag0;
-        bool keep = false;
+    while (u < u_end) {  // one run: a Gaussian block and consecutive frames of its group
+        while (u >= sg.start[gi + 1]) ++gi;
+        const FrameDev& F0 = tab[sg.frame[sg.first[gi]]];
+        const uint32_t n = F0.n;
+        const uint32_t nq = sg.first[gi + 1] - sg.first[gi];
+        const uint32_t local = u - sg.start[gi];
+        const uint32_t gb = local / nq;
+        const uint32_t qa = local - gb * nq;
+        const uint32_t run = min(u_end - u, nq - qa);
+        const uint32_t i = gb * kBlock + threadIdx.x;
+        const bool valid = i < n;
+        SliceFixed S;
+        float mu_p[3] = {0.f, 0.f, 0.f}, mu_d[3] = {0.f, 0.f, 0.f}, cv32[6];
+        float mu_t = 0.f, alpha = 0.f;
+        bool cv_fin = false;
+        uint32_t flag0 = 0;
         if (valid) {
-            SliceView W;
-            const double md[3] = {(double)mu_d[0], (double)mu_d[1], (double)mu_d[2]};
-            double d[3], rn;
-            view_direction(F, mu_p, d, rn);
-            slice_view<false>(S, (double)F.t, d, rn, (double)mu_t, md, F.lambda_t, F.lambda_d, W);
-            float mc[3], cv[6], ac;
-            slice_outputs(S, W, mu_p, cv32, cv_fin, alpha, mc, cv, ac, flag);
-            const size_t g0 = F.g0;
+            // every load of the Gaussian is issued before the first LDS store
+            float sh[48];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) mu_c[3 * g0 + (size_t)a * n + i] = mc[a];
+            for (int j = 0; j < 48; ++j) sh[j] = gload(F0.sh, (size_t)j * n + i);
+            double L[28];
+            load_L(F0.L, n, i, L);
 #pragma unroll
-            for (int e = 0; e < 6; ++e) cov_c[6 * g0 + (size_t)e * n + i] = cv[e];
-            alpha_c[g0 + i] = ac;
-            keep = project_emit(F, i, ac, mc, cv, ShLds{s_sh}, splat, rect, depth_key);
+            for (int a = 0; a < 3; ++a) mu_p[a] = gload(F0.mu_p, (size_t)a * n + i);
+            mu_t = gload(F0.mu_t, i);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) mu_d[k] = gload(F0.mu_d, (size_t)k * n + i);
+            alpha = gload(F0.alpha, i);
+            // each lane reads back only what it wrote (this run's or the
+            // previous run's column of its own): no barrier needed
+#pragma unroll
+            for (int j = 0; j < 48; ++j) s_sh[j * kBlock + threadIdx.x] = sh[j];
+            slice_fixed(L, S, flag0);
+            cv_fin = slice_cov(S, cv32);
         }
-        wave_flags(flag, counts, f);
-        wave_kept(keep, counts, f);
+        const uint32_t qb = sg.first[gi] + qa, qe = qb + run;
+        for (uint32_t q = qb; q < qe; ++q) {
+            const int f = sg.frame[q];
+            const FrameDev& F = tab[f];
+            uint32_t flag = flag0;
+            bool keep = false;
+            if (valid) {
+                SliceView W;
+                const double md[3] = {(double)mu_d[0], (double)mu_d[1], (double)mu_d[2]};
+                double d[3], rn;
+                view_direction(F, mu_p, d, rn);
+                slice_view<false>(S, (double)F.t, d, rn, (double)mu_t, md, F.lambda_t, F.lambda_d, W);
+                float mc[3], cv[6], ac;
+                slice_outputs(S, W, mu_p, cv32, cv_fin, alpha, mc, cv, ac, flag);
+                const size_t g0 = F.g0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) mu_c[3 * g0 + (size_t)a * n + i] = mc[a];
+#pragma unroll
+                for (int e = 0; e < 6; ++e) cov_c[6 * g0 + (size_t)e * n + i] = cv[e];
+                alpha_c[g0 + i] = ac;
+                keep = project_emit(F, i, ac, mc, cv, ShLds{s_sh}, splat, rect, depth_key);
+            }
+            wave_flags(flag, counts, f);
+            wave_kept(keep, counts, f);
+        }
+        u += run;
     }
 }
 
