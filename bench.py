@@ -46,8 +46,8 @@ FP32_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 RASTER_OPS_PER_TEST = 12
 RASTER_OPS_PER_CONTRIBUTION = 12
 RASTER_SRC_DIR = "paper_2503_07946_amd/csrc"
-RASTER_SRC_SHA256 = "f44db6ffd19c24f8d323fcf11bc98a24817336664c84a6228c29c2e78c3a1371"
-RASTER_TRAFFIC_BYTES = 2343108928       # (987846 KiB x 2 + 312500 KiB) x 1024
+RASTER_SRC_SHA256 = "1af3b597f43a6fb95c763e53f4604a2c2c430331460f896163d45bc1a24ac01b"
+RASTER_TRAFFIC_BYTES = 2344052736       # (988307 KiB x 2 + 312500 KiB) x 1024
 RASTER_VALU_INSTRUCTIONS = 1108255228   # SQ_INSTS_VALU per launch (wave64 instructions)
 
 

@@ -33,19 +33,36 @@ __global__ __launch_bounds__(kBlock, 3) void k_slice_project(const FrameDev* __r
 {
     const uint32_t lb = xcd_contiguous(blockIdx.x, gridDim.x);
     const uint32_t units = sg.start[sg.ng];
-    uint32_t u = (uint32_t)((uint64_t)lb * units / gridDim.x);
-    const uint32_t u_end = (uint32_t)((uint64_t)(lb + 1) * units / gridDim.x);
-    int gi = group_of_unit(sg, u);
+    uint32_t lo = (uint32_t)((uint64_t)lb * units / gridDim.x);
+    uint32_t hi = (uint32_t)((uint64_t)(lb + 1) * units / gridDim.x);
+    // Odd blocks take their runs last to first: a Gaussian block split
+    // between the end of one share and the start of the next is then read by
+    // both blocks at about the same time, while it is still in L2.
+    const bool rev = lb & 1u;
+    int gi = group_of_unit(sg, rev ? hi - 1u : lo);
     __shared__ float s_sh[48 * kBlock];
-    while (u < u_end) {  // one run: a Gaussian block and consecutive frames of its group
-        while (u >= sg.start[gi + 1]) ++gi;
+    while (lo < hi) {  // one run: a Gaussian block and consecutive frames of its group
+        uint32_t ua, ub;  // the run's units [ua, ub)
+        uint32_t nq, gb;
+        if (!rev) {
+            ua = lo;
+            while (ua >= sg.start[gi + 1]) ++gi;
+            nq = sg.first[gi + 1] - sg.first[gi];
+            gb = (ua - sg.start[gi]) / nq;
+            ub = min(hi, sg.start[gi] + (gb + 1) * nq);
+            lo = ub;
+        } else {
+            ub = hi;
+            while (ub - 1u < sg.start[gi]) --gi;
+            nq = sg.first[gi + 1] - sg.first[gi];
+            gb = (ub - 1u - sg.start[gi]) / nq;
+            ua = max(lo, sg.start[gi] + gb * nq);
+            hi = ua;
+        }
         const FrameDev& F0 = tab[sg.frame[sg.first[gi]]];
         const uint32_t n = F0.n;
-        const uint32_t nq = sg.first[gi + 1] - sg.first[gi];
-        const uint32_t local = u - sg.start[gi];
-        const uint32_t gb = local / nq;
-        const uint32_t qa = local - gb * nq;
-        const uint32_t run = min(u_end - u, nq - qa);
+        const uint32_t qa = ua - sg.start[gi] - gb * nq;
+        const uint32_t run = ub - ua;
         const uint32_t i = gb * kBlock + threadIdx.x;
         const bool valid = i < n;
         SliceFixed S;
@@ -98,7 +115,6 @@ __global__ __launch_bounds__(kBlock, 3) void k_slice_project(const FrameDev* __r
             wave_flags(flag, counts, f);
             wave_kept(keep, counts, f);
         }
-        u += run;
     }
 }
 

@@ -58,13 +58,18 @@ def test_batch_overflow_defers_only_frames_that_do_not_fit(R):
     assert np.array_equal(b.frames[0].image.cpu().numpy(), alone.frames[0].image.cpu().numpy())
 
 
-def test_fused_slice_project_equals_separate_calls(R):
+@pytest.mark.parametrize("nA,nB", [(3000, 1500), (120000, 60000)])
+def test_fused_slice_project_equals_separate_calls(R, nA, nB):
     """sd7_slice_project over scene groups writes bitwise what sd7_slice then
     sd7_project write: frames of two scenes interleaved (groups of 3 and 2),
-    a scene with no Gaussians, and a scene with a non-positive L diagonal."""
+    a scene with no Gaussians, and a scene with a non-positive L diagonal.
+    The small case has fewer (Gaussian block, frame) units than resident
+    blocks (one unit per block); the large one 1877 units over 768 blocks, so
+    blocks take several runs, in both walking orders, across Gaussian-block
+    and scene-group boundaries."""
     from paper_2503_07946_amd.render import GaussianScene
-    sA = scenegen.make_scene(3000, 41, sigma_off=0.15)
-    sB = scenegen.make_scene(1500, 42)
+    sA = scenegen.make_scene(nA, 41, sigma_off=0.15)
+    sB = scenegen.make_scene(nB, 42)
     sB.L[0, :40] = -sB.L[0, :40]                  # L_00 <= 0: flagged and culled
     vA = scenegen.make_views(3, 41, r=3.0, W=96, H=64)
     vB = scenegen.make_views(2, 42, r=2.5, W=40, H=72, lam=0.5)
@@ -72,7 +77,7 @@ def test_fused_slice_project_equals_separate_calls(R):
     empty = GaussianScene(*(torch.zeros((k, 0), device="cuda").reshape(-1) if k == 1 else
                             torch.zeros((k, 0), device="cuda") for k in (3, 1, 3, 28, 1, 48)))
     items = [(gA, vA[0]), (gB, vB[0]), (empty, vA[1]), (gA, vA[1]), (gB, vB[1]), (gA, vA[2])]
-    print("[batch] fused vs separate slice/project, 6 frames", flush=True)
+    print(f"[batch] fused vs separate slice/project, 6 frames, {nA} + {nB} Gaussians", flush=True)
     sep = R.batch(R.make_frames(items), 1 << 16)
     fus = R.batch(R.make_frames(items), 1 << 16)
     R.stage("sd7_slice", sep)
