@@ -58,15 +58,16 @@ def test_batch_overflow_defers_only_frames_that_do_not_fit(R):
     assert np.array_equal(b.frames[0].image.cpu().numpy(), alone.frames[0].image.cpu().numpy())
 
 
-@pytest.mark.parametrize("nA,nB", [(3000, 1500), (120000, 60000)])
-def test_fused_slice_project_equals_separate_calls(R, nA, nB):
+@pytest.mark.parametrize("nA,nB,empty_at", [(3000, 1500, 2), (120000, 60000, 2), (120000, 60000, 0)])
+def test_fused_slice_project_equals_separate_calls(R, nA, nB, empty_at):
     """sd7_slice_project over scene groups writes bitwise what sd7_slice then
     sd7_project write: frames of two scenes interleaved (groups of 3 and 2),
     a scene with no Gaussians, and a scene with a non-positive L diagonal.
     The small case has fewer (Gaussian block, frame) units than resident
     blocks (one unit per block); the large one 1877 units over 768 blocks, so
     blocks take several runs, in both walking orders, across Gaussian-block
-    and scene-group boundaries."""
+    and scene-group boundaries.  The scene with no Gaussians (a group with no
+    units) comes last among the groups or first."""
     from paper_2503_07946_amd.render import GaussianScene
     sA = scenegen.make_scene(nA, 41, sigma_off=0.15)
     sB = scenegen.make_scene(nB, 42)
@@ -76,8 +77,10 @@ def test_fused_slice_project_equals_separate_calls(R, nA, nB):
     gA, gB = GaussianScene.from_host(sA), GaussianScene.from_host(sB)
     empty = GaussianScene(*(torch.zeros((k, 0), device="cuda").reshape(-1) if k == 1 else
                             torch.zeros((k, 0), device="cuda") for k in (3, 1, 3, 28, 1, 48)))
-    items = [(gA, vA[0]), (gB, vB[0]), (empty, vA[1]), (gA, vA[1]), (gB, vB[1]), (gA, vA[2])]
-    print(f"[batch] fused vs separate slice/project, 6 frames, {nA} + {nB} Gaussians", flush=True)
+    items = [(gA, vA[0]), (gB, vB[0]), (gA, vA[1]), (gB, vB[1]), (gA, vA[2])]
+    items.insert(empty_at, (empty, vA[1]))
+    print(f"[batch] fused vs separate slice/project, 6 frames, {nA} + {nB} Gaussians, "
+          f"empty scene at {empty_at}", flush=True)
     sep = R.batch(R.make_frames(items), 1 << 16)
     fus = R.batch(R.make_frames(items), 1 << 16)
     R.stage("sd7_slice", sep)
