@@ -3,6 +3,7 @@ times (the first batch of a step: 25 of the 50 views of 800x800 over 200,000
 Gaussians, in one set of launches), checked on
 outputs the oracle can compute at this size: the whole slice, the integer
 stage re-executed on the CPU, and sampled pixel crops of the image.  Also the
+full variant with adaptive refinement in the same launch configuration, the
 training workload (500,000 Gaussians at 1352x1014, forward + backward with the
 upstream gradient restricted to a crop) and the ill-conditioned 4M-Gaussian
 1080p stress scene."""
@@ -95,6 +96,50 @@ def test_c1_sampled_crops(R, c1, c1_batch, report):
         err, nflag = image_check(img[:, 384:416, 384:416], ora)
         report("c1_crop", frame=f, crop=crop, max_err=err, flagged=nflag)
         assert err <= 1e-4
+
+
+def test_c1_agr_batch_slice_and_crop(R, c1, report):
+    """The full variant with adaptive refinement in the benchmark's launch
+    configuration (the same 25 views, the 200,000 Gaussians refined with
+    scenegen.agr_weights(1)): the sliced statistics of every Gaussian of the
+    batch's last frame and the centre crop of its first, against the FP64
+    oracle with the refinement's tolerances."""
+    from paper_2503_07946_amd.render import GaussianScene
+    from tests.test_gpu_agr import AGR_REL, EPS_MU, log_alpha_sensitivity
+    scene, views = c1
+    w = scenegen.agr_weights(1)
+    gs = GaussianScene.from_host(scene, agr=w)
+    print("[fullsize] AGR: 200k Gaussians, batch of 25 x 800x800", flush=True)
+    b = R.render_frames(R.make_frames([(gs, v) for v in views]))
+    torch.cuda.synchronize()
+    f = len(views) - 1
+    v = views[f]
+    ora = oracle.slice_(scene, v, agr_weights=w)
+    ref = oracle.agr(scene, v.t, w)
+    ok = ora.status == 0
+    assert ok.mean() > 0.5
+    mscale = np.maximum(np.abs(ora.mu_c).max(0), np.abs(ref.mu_p).max(0))
+    cscale = np.abs(ora.cov_c).max(0)
+    mu = b.mu_c(f).cpu().numpy().astype(np.float64)
+    cov = b.cov_c(f).cpu().numpy().astype(np.float64)
+    ac = b.alpha_c(f).cpu().numpy().astype(np.float64)
+    tol_mu = np.maximum(slice_tolerance(ora.mu_c, mscale), AGR_REL * mscale)
+    tol_cv = np.maximum(slice_tolerance(ora.cov_c, cscale), AGR_REL * cscale)
+    tol_ac = np.maximum(slice_tolerance(ora.alpha_c, ora.alpha_c),
+                        (AGR_REL + EPS_MU * log_alpha_sensitivity(ref, v)) * ora.alpha_c)
+    e_mu = (np.abs(mu - ora.mu_c) / np.maximum(mscale, 1e-30))[:, ok].max()
+    e_cv = (np.abs(cov - ora.cov_c) / np.maximum(cscale, 1e-30))[:, ok].max()
+    e_ac = (np.abs(ac - ora.alpha_c) / np.maximum(ora.alpha_c, 1e-30))[ok].max()
+    report("c1_agr_slice", frame=f, mu_rel=float(e_mu), cov_rel=float(e_cv), alpha_rel=float(e_ac))
+    assert np.all(np.abs(mu - ora.mu_c)[:, ok] <= tol_mu[:, ok]), e_mu
+    assert np.all(np.abs(cov - ora.cov_c)[:, ok] <= tol_cv[:, ok]), e_cv
+    assert np.all(np.abs(ac - ora.alpha_c)[ok] <= tol_ac[ok]), e_ac
+    crop = (384, 384, 32, 32)
+    img = b.frames[0].image.cpu().numpy()
+    o = oracle.render(scene, views[0], crop=crop, agr_weights=w)
+    err, nflag = image_check(img[:, 384:416, 384:416], o)
+    report("c1_agr_crop", frame=0, crop=crop, max_err=err, flagged=nflag)
+    assert err <= 1e-4
 
 
 def test_c2_training_step_crop_gradients(R, report):
