@@ -93,7 +93,9 @@ typedef int32_t sd7_status;
 #define SD7_CNT_PAIRS 1     /* (tile, Gaussian) pairs of the frame */
 #define SD7_CNT_PAIR_BASE 2 /* first arena slot of the frame's pairs */
 #define SD7_CNT_FLAGS 3     /* SD7_FLAG_* bits */
-#define SD7_CNT_WORDS 16
+#define SD7_CNT_NEEDED 4    /* pairs the frame needs, written by sd7_bin whether or not they
+                               fit (on SD7_FLAG_PAIR_OVERFLOW: the share a re-run must give it) */
+#define SD7_CNT_WORDS 16    /* words 5..15 are internal scratch of sd7_bin */
 
 typedef struct sd7_ctx sd7_ctx;
 typedef void* sd7_stream; /* a hipStream_t */
@@ -344,9 +346,11 @@ sd7_status sd7_rasterize(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t 
 sd7_status sd7_render(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t pair_capacity,
                       void* ws, size_t ws_bytes, sd7_stream stream);
 
-/* Reverse of the compositing (front-to-back recomputation; no per-pixel
- * list state is stored): reads each frame's dL_dimage, image, final_T, last
- * and the bins; writes d_splat (zeroed first, then accumulated). */
+/* Reverse of the compositing (Sec. 4.4, differentiable rasterization): each
+ * pixel walks the list entries it consumed back to front from its final_T,
+ * recomputing transmittance and the colour behind each entry (no per-pixel
+ * list state is stored).  Reads each frame's dL_dimage, final_T, last and the
+ * bins; writes d_splat (zeroed first, then accumulated). */
 sd7_status sd7_rasterize_backward(sd7_ctx* ctx, const sd7_frame* frames, int nf,
                                   int64_t pair_capacity, void* ws, size_t ws_bytes,
                                   sd7_stream stream);

@@ -54,12 +54,22 @@ class OraView(ctypes.Structure):
 
 
 class OraFlagCfg(ctypes.Structure):
-    _fields_ = [("tau_alpha", ctypes.c_double), ("tau_T", ctypes.c_double),
-                ("tau_z", ctypes.c_double), ("impact_min", ctypes.c_double)]
+    _fields_ = [("k_mu", ctypes.c_double), ("k_uv", ctypes.c_double), ("k_s", ctypes.c_double),
+                ("k_eval", ctypes.c_double), ("k_ac", ctypes.c_double), ("k_T", ctypes.c_double),
+                ("k_z", ctypes.c_double),
+                ("impact_min", ctypes.c_double)]
 
 
-# Decision bands used by the parity protocol (FP32 GPU vs FP64 oracle).
-DEFAULT_FLAGS = dict(tau_alpha=2e-4, tau_T=2e-4, tau_z=4e-6, impact_min=1e-5)
+# The parity protocol's model of an FP32 evaluation of the path (oracle7d.h,
+# ora_flagcfg): coefficients, in units of 2^-24, of the error terms that set
+# each decision's band.  The opacity-test coefficients are the smallest (on a
+# grid of powers of two) under which every exponent error measured on the
+# MI355X path near the threshold stays below half its band (small, correlated,
+# 200k-, 500k- and 4M-Gaussian workloads, 175k samples); k_ac is one rounding
+# of alpha_cond, twice; k_T one fused multiply-add per step, four times;
+# k_z = 2 bounds the depth error of FP32-rounded conditional means,
+# 2^-24 (sqrt(3) max|mu_c| + z), outright.
+DEFAULT_FLAGS = dict(k_mu=1.0, k_uv=2.0, k_s=1.0, k_eval=2.0, k_ac=2.0, k_T=4.0, k_z=2.0, impact_min=1e-5)
 
 _lib = None
 
@@ -74,17 +84,19 @@ def lib():
         i64 = ctypes.c_int64
         L.ora_slice.argtypes = [i64, P, P, P, P, P, ctypes.POINTER(OraView), P, P, P, P, P, P]
         L.ora_slice.restype = ctypes.c_int
-        L.ora_project.argtypes = [i64, P, P, P, P, ctypes.POINTER(OraView), P, P, P, P, P, P]
+        L.ora_project.argtypes = [i64, P, P, P, P, ctypes.POINTER(OraView), P, P, P, P, P, P, P]
         L.ora_project.restype = i64
         L.ora_order.argtypes = [i64, P, P, P]
         L.ora_order.restype = i64
-        L.ora_composite.argtypes = [i64, P, P, P, P, P, i64, P, ctypes.POINTER(OraView),
+        L.ora_fp32_model.argtypes = [i64, P, P, ctypes.POINTER(OraView), P]
+        L.ora_fp32_model.restype = None
+        L.ora_composite.argtypes = [i64, P, P, P, P, P, P, i64, P, ctypes.POINTER(OraView),
                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                    ctypes.POINTER(OraFlagCfg), P, P, P, P, P]
+                                    ctypes.POINTER(OraFlagCfg), P, P, P, P, P, P]
         L.ora_composite.restype = ctypes.c_int
         L.ora_render.argtypes = [i64, P, P, P, P, P, P, ctypes.POINTER(OraView),
                                  ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                 ctypes.POINTER(OraFlagCfg), P, P, P, P, P]
+                                 ctypes.POINTER(OraFlagCfg), P, P, P, P, P, P]
         L.ora_render.restype = ctypes.c_int
         L.ora_sh_basis.argtypes = [ctypes.c_double] * 3 + [P]
         L.ora_agr_encoding.argtypes = [ctypes.c_double, P]
@@ -205,20 +217,22 @@ class Projected:
     conic: np.ndarray    # [3][n]
     depth: np.ndarray    # [n]
     rgb: np.ndarray      # [3][n]
-    rect: np.ndarray     # [4][n] int32
+    rect: np.ndarray     # [4][n] int32 tile range x0, y0, x1, y1 (x1, y1 exclusive)
     visible: np.ndarray  # [n] bool
+    box: np.ndarray      # [4][n] opacity footprint in pixels (x0, y0, x1, y1)
 
 
 def project(sliced: Sliced, sh, view) -> Projected:
     n = sliced.alpha_c.shape[0]
     mean2d = np.zeros((2, n)); conic = np.zeros((3, n)); depth = np.zeros(n)
     rgb = np.zeros((3, n)); rect = np.zeros((4, n), np.int32); vis = np.zeros(n, np.uint8)
+    box = np.zeros((4, n))
     sh = _f64(sh)
     ov = ora_view(view)
     lib().ora_project(n, _p(np.ascontiguousarray(sliced.mu_c)), _p(np.ascontiguousarray(sliced.cov_c)),
                       _p(np.ascontiguousarray(sliced.alpha_c)), _p(sh), ctypes.byref(ov),
-                      _p(mean2d), _p(conic), _p(depth), _p(rgb), _p(rect), _p(vis))
-    return Projected(mean2d, conic, depth, rgb, rect, vis.astype(bool))
+                      _p(mean2d), _p(conic), _p(depth), _p(rgb), _p(rect), _p(vis), _p(box))
+    return Projected(mean2d, conic, depth, rgb, rect, vis.astype(bool), box)
 
 
 def order(proj: Projected) -> np.ndarray:
@@ -236,40 +250,57 @@ class Image:
     ncontrib: np.ndarray  # [h][w]
     chash: np.ndarray     # [h][w] uint64 hash of the contributor set
     flags: np.ndarray     # [h][w] uint32 ORA_FLAG_* bits
+    fbound: np.ndarray    # [h][w] bound on the pixel's change from in-band decisions
 
 
-def composite(sliced: Sliced, proj: Projected, view, crop=None, flags=None) -> Image:
+FLAG_ALPHA, FLAG_T, FLAG_DEPTH = 1, 2, 4
+
+
+def fp32_model(sliced: Sliced, view) -> np.ndarray:
+    """Per-Gaussian scales of the FP32 error model [5][n] (ora_fp32_model)."""
+    n = sliced.alpha_c.shape[0]
+    out = np.zeros((5, n))
+    ov = ora_view(view)
+    lib().ora_fp32_model(n, _p(np.ascontiguousarray(sliced.mu_c)), _p(np.ascontiguousarray(sliced.cov_c)),
+                         ctypes.byref(ov), _p(out))
+    return out
+
+
+def composite(sliced: Sliced, proj: Projected, view, crop=None, flags=None, banded=True) -> Image:
     x0, y0, w, h = crop if crop is not None else (0, 0, view.W, view.H)
     n = proj.depth.shape[0]
     ordv = np.ascontiguousarray(order(proj))
     img = np.zeros((3, h, w)); T = np.zeros((h, w)); nc = np.zeros((h, w), np.int32)
-    ch = np.zeros((h, w), np.uint64); fl = np.zeros((h, w), np.uint32)
+    ch = np.zeros((h, w), np.uint64); fl = np.zeros((h, w), np.uint32); fb = np.zeros((h, w))
     fc = flagcfg(**(flags or {}))
+    ep = fp32_model(sliced, view) if banded else None
     ov = ora_view(view)
     lib().ora_composite(n, _p(proj.mean2d), _p(proj.conic), _p(np.ascontiguousarray(sliced.alpha_c)),
-                        _p(proj.depth), _p(proj.rgb), len(ordv), _p(ordv), ctypes.byref(ov),
-                        x0, y0, w, h, ctypes.byref(fc), _p(img), _p(T), _p(nc), _p(ch), _p(fl))
-    return Image(img, T, nc, ch, fl)
+                        _p(proj.depth), _p(proj.rgb), _p(ep) if ep is not None else None, len(ordv),
+                        _p(ordv), ctypes.byref(ov), x0, y0, w, h, ctypes.byref(fc) if banded else None,
+                        _p(img), _p(T), _p(nc), _p(ch), _p(fl), _p(fb))
+    return Image(img, T, nc, ch, fl, fb)
 
 
-def render(scene, view, crop=None, flags=None, agr_weights=None) -> Image:
+def render(scene, view, crop=None, flags=None, agr_weights=None, banded=True) -> Image:
     """Full FP64 forward of one view (optionally a pixel crop x0, y0, w, h),
-    with the scene first refined by AGR when weights are given."""
+    with the scene first refined by AGR when weights are given.  banded:
+    also flag in-band decisions and bound their effect (flags, fbound)."""
     if agr_weights is not None:
         scene = agr(scene, view.t, agr_weights)
     x0, y0, w, h = crop if crop is not None else (0, 0, view.W, view.H)
     n = scene.n
     img = np.zeros((3, h, w)); T = np.zeros((h, w)); nc = np.zeros((h, w), np.int32)
-    ch = np.zeros((h, w), np.uint64); fl = np.zeros((h, w), np.uint32)
+    ch = np.zeros((h, w), np.uint64); fl = np.zeros((h, w), np.uint32); fb = np.zeros((h, w))
     fc = flagcfg(**(flags or {}))
     arrs = [_f64(scene.mu_p), _f64(scene.mu_t), _f64(scene.mu_d), _f64(scene.L),
             _f64(scene.alpha), _f64(scene.sh)]
     ov = ora_view(view)
     rc = lib().ora_render(n, *[_p(a) for a in arrs], ctypes.byref(ov), x0, y0, w, h,
-                          ctypes.byref(fc), _p(img), _p(T), _p(nc), _p(ch), _p(fl))
+                          ctypes.byref(fc) if banded else None, _p(img), _p(T), _p(nc), _p(ch), _p(fl), _p(fb))
     if rc != 0:
         raise MemoryError("oracle render failed to allocate")
-    return Image(img, T, nc, ch, fl)
+    return Image(img, T, nc, ch, fl, fb)
 
 
 def sh_basis(x: float, y: float, z: float) -> np.ndarray:

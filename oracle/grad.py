@@ -155,9 +155,21 @@ def project_t(mu_c, Sc, alpha_c, sh, view):
 
 def render_t(P: dict, view, crop=None, chunk_rows: int = 16):
     """Differentiable FP64 render of the crop (x0, y0, w, h): image [3,h,w]."""
-    x0, y0, w, h = crop if crop is not None else (0, 0, view.W, view.H)
     mu_c, Sc, alpha_c = slice_t(P, view)
-    mean2d, conic, depth, rgb, vis, box = project_t(mu_c, Sc, alpha_c, P["sh"], view)
+    return render_sliced_t(mu_c, Sc, alpha_c, P["sh"], view, crop, chunk_rows)
+
+
+def render_sliced_t(mu_c, Sc, alpha_c, sh, view, crop=None, chunk_rows: int = 16):
+    """Projection and compositing (Sec. 4.4) of sliced Gaussians: image [3,h,w]
+    of the crop (x0, y0, w, h)."""
+    mean2d, conic, depth, rgb, vis, box = project_t(mu_c, Sc, alpha_c, sh, view)
+    return render_splats_t(mean2d, conic, alpha_c, rgb, depth, vis, box, view, crop, chunk_rows)
+
+
+def render_splats_t(mean2d, conic, alpha_c, rgb, depth, vis, box, view, crop=None, chunk_rows: int = 16):
+    """Front-to-back compositing (Sec. 4.4) of projected splats: image [3,h,w]
+    of the crop (x0, y0, w, h)."""
+    x0, y0, w, h = crop if crop is not None else (0, 0, view.W, view.H)
     with torch.no_grad():
         # Gaussians whose footprint box holds no pixel centre of the crop have
         # alpha < ALPHA_MIN at every crop pixel and contribute nothing.
@@ -216,3 +228,42 @@ def grad(scene, view, dL_dimage: np.ndarray, crop=None):
 def l1_grad_image(image: np.ndarray, target: np.ndarray) -> np.ndarray:
     """d/dC of mean |C - target| over all 3HW entries, with sign(0) = 0."""
     return np.sign(image - target) / image.size
+
+
+SPLAT = ("u", "v", "a", "b", "c", "alpha_c", "r", "g", "b_")   # splat parameters, in d_splat order
+SPLAT_GROUPS = ((0, 2), (2, 5), (5, 6), (6, 9))   # mean2d, conic, opacity, colour
+
+
+def grad_splats(scene, view, dL_dimage: np.ndarray, crop=None) -> np.ndarray:
+    """Gradient of <dL, image> with respect to each Gaussian's splat (Sec. 4.4),
+    [9][n]: mean2d (u, v), conic (a, b, c) of q = a dx^2 + 2 b dx dy + c dy^2,
+    the conditional opacity, and the (clamped) colour."""
+    P = scene_tensors(scene, requires_grad=False)
+    mu_c, Sc, alpha_c = slice_t(P, view)
+    mean2d, conic, depth, rgb, vis, box = project_t(mu_c, Sc, alpha_c, P["sh"], view)
+    leaves = [x.detach().requires_grad_(True) for x in (mean2d, conic, alpha_c, rgb)]
+    img = render_splats_t(*leaves[:2], leaves[2], leaves[3], depth.detach(), vis, box, view, crop)
+    (img * torch.tensor(np.asarray(dL_dimage), dtype=torch.float64)).sum().backward()
+    m, c, a, r = (x.grad for x in leaves)
+    return np.concatenate([m.numpy().T, c.numpy().T, a.numpy()[None], r.numpy().T], 0)
+
+
+def splat_jacobian(scene, view) -> dict:
+    """Jacobian of each Gaussian's splat (the 9 values of grad_splats, through
+    the slice and the projection) with respect to its own parameters, by one
+    reverse pass per splat value (the splat of Gaussian i depends only on the
+    parameters of Gaussian i): {param: [9][planes][n]}.  Zero for culled
+    Gaussians' clamped branches as in the forward."""
+    P = scene_tensors(scene)
+    mu_c, Sc, alpha_c = slice_t(P, view)
+    mean2d, conic, depth, rgb, vis, box = project_t(mu_c, Sc, alpha_c, P["sh"], view)
+    outs = [mean2d[:, 0], mean2d[:, 1], conic[:, 0], conic[:, 1], conic[:, 2], alpha_c,
+            rgb[:, 0], rgb[:, 1], rgb[:, 2]]
+    n = scene.n
+    J = {k: np.zeros((len(SPLAT), 1 if P[k].dim() == 1 else P[k].shape[0], n)) for k in PARAMS}
+    for j, y in enumerate(outs):
+        gs = torch.autograd.grad(y.sum(), [P[k] for k in PARAMS], retain_graph=True, allow_unused=True)
+        for k, gk in zip(PARAMS, gs):
+            if gk is not None:
+                J[k][j] = gk.numpy().reshape(J[k].shape[1], n)
+    return J

@@ -238,7 +238,7 @@ void ora_sh_basis(double x, double y, double z, double* Y) { sh_basis(x, y, z, Y
 
 int64_t ora_project(int64_t n, const double* mu_c, const double* cov_c, const double* alpha_c,
                     const double* sh, const ora_view* v, double* mean2d, double* conic,
-                    double* depth, double* rgb, int32_t* rect, uint8_t* visible)
+                    double* depth, double* rgb, int32_t* rect, uint8_t* visible, double* box)
 {
     double R[9], c[3];
     for (int k = 0; k < 9; ++k) R[k] = v->R[k];
@@ -298,10 +298,15 @@ int64_t ora_project(int64_t n, const double* mu_c, const double* cov_c, const do
             }
         }
         int32_t rc[4] = {0, 0, 0, 0};
+        double bx[4] = {0, 0, 0, 0};
         if (vis) {
             /* exact bounding box of {alpha >= ALPHA_MIN}: q <= 2 ln(alpha_c / ALPHA_MIN) */
             double k = 2.0 * log(ac / ALPHA_MIN);
             double hx = sqrt(k * S00), hy = sqrt(k * S11);
+            bx[0] = u - hx;
+            bx[1] = vv - hy;
+            bx[2] = u + hx;
+            bx[3] = vv + hy;
             double tx0 = floor((u - hx) / TILE), tx1 = floor((u + hx) / TILE);
             double ty0 = floor((vv - hy) / TILE), ty1 = floor((vv + hy) / TILE);
             if (tx0 < 0) tx0 = 0;
@@ -338,6 +343,8 @@ int64_t ora_project(int64_t n, const double* mu_c, const double* cov_c, const do
         depth[g] = x[2];
         for (int ch = 0; ch < 3; ++ch) rgb[(int64_t)ch * n + g] = col[ch];
         for (int k = 0; k < 4; ++k) rect[(int64_t)k * n + g] = rc[k];
+        if (box)
+            for (int k = 0; k < 4; ++k) box[(int64_t)k * n + g] = bx[k];
         visible[g] = (uint8_t)vis;
         nvis += vis;
     }
@@ -380,14 +387,94 @@ int64_t ora_order(int64_t n, const double* depth, const uint8_t* visible, int64_
     return m;
 }
 
+/* ---------------------------------------------------------------------- */
+/* FP32 decision bands of the parity protocol (not part of the method)     */
+/* ---------------------------------------------------------------------- */
+
+/* Per Gaussian, the scales of the error an FP32 evaluation of the path makes
+ * in its splat (mean2d, conic, depth), given FP32-rounded sliced statistics:
+ *   errpar[0] = max(fx, fy) / z * max_k |mu_c,k|  (mean2d error per unit of
+ *               relative error of mu_c, in pixels)
+ *   errpar[1..3] = (|M| |Sigma_c| |M|^T)_{00, 01, 11} with M = J R: a bound on
+ *               the 2D covariance's change per unit of relative error of the
+ *               entries of Sigma_c (no cancellation credited)
+ *   errpar[4] = max_k |mu_c,k| + |z|  (depth error per unit relative error)
+ * Culled Gaussians get zeros. */
+void ora_fp32_model(int64_t n, const double* mu_c, const double* cov_c, const ora_view* v, double* errpar)
+{
+    double R[9], c[3];
+    for (int k = 0; k < 9; ++k) R[k] = v->R[k];
+    for (int k = 0; k < 3; ++k) c[k] = v->c[k];
+    const double fx = v->fx, fy = v->fy;
+    const double limx = JCLAMP * (0.5 * v->W) / fx, limy = JCLAMP * (0.5 * v->H) / fy;
+#pragma omp parallel for schedule(static)
+    for (int64_t g = 0; g < n; ++g) {
+        double m[3], x[3], mmax = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            m[k] = mu_c[(int64_t)k * n + g] - c[k];
+            const double a = fabs(mu_c[(int64_t)k * n + g]);
+            if (a > mmax) mmax = a;
+        }
+        for (int i = 0; i < 3; ++i) x[i] = R[3 * i] * m[0] + R[3 * i + 1] * m[1] + R[3 * i + 2] * m[2];
+        double e[5] = {0, 0, 0, 0, 0};
+        if (x[2] > Z_NEAR) {
+            double rx = x[0] / x[2], ry = x[1] / x[2];
+            rx = rx > limx ? limx : (rx < -limx ? -limx : rx);
+            ry = ry > limy ? limy : (ry < -limy ? -limy : ry);
+            const double J[2][3] = {{fx / x[2], 0.0, -fx * rx / x[2]}, {0.0, fy / x[2], -fy * ry / x[2]}};
+            double M[2][3];
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 3; ++j) M[i][j] = fabs(J[i][0] * R[j] + J[i][1] * R[3 + j] + J[i][2] * R[6 + j]);
+            const double S[3][3] = {{fabs(cov_c[g]), fabs(cov_c[n + g]), fabs(cov_c[2 * n + g])},
+                                    {fabs(cov_c[n + g]), fabs(cov_c[3 * n + g]), fabs(cov_c[4 * n + g])},
+                                    {fabs(cov_c[2 * n + g]), fabs(cov_c[4 * n + g]), fabs(cov_c[5 * n + g])}};
+            double A[2][2];
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j) {
+                    double s = 0.0;
+                    for (int k = 0; k < 3; ++k)
+                        for (int l = 0; l < 3; ++l) s += M[i][k] * S[k][l] * M[j][l];
+                    A[i][j] = s;
+                }
+            e[0] = (fx > fy ? fx : fy) / x[2] * mmax;
+            e[1] = A[0][0];
+            e[2] = A[0][1];
+            e[3] = A[1][1];
+            e[4] = mmax + fabs(x[2]);
+        }
+        for (int k = 0; k < 5; ++k) errpar[(int64_t)k * n + g] = e[k];
+    }
+}
+
+/* A decision the oracle takes within its FP32 band, for the per-pixel bound
+ * on how much the image may change if an FP32 evaluation takes it the other
+ * way.  kind: 0 skipped at ALPHA_MIN, 1 blended at ALPHA_MIN, 2 stopped at
+ * T_MIN, 3 continued at T_MIN. */
+typedef struct {
+    int kind;
+    double a, T, C[3], rgb[3];
+} ora_event;
+#define ORA_MAX_EVENTS 32
+
 int ora_composite(int64_t n, const double* mean2d, const double* conic, const double* alpha_c,
-                  const double* depth, const double* rgb, int64_t m, const int64_t* order,
-                  const ora_view* v, int x0, int y0, int w, int h, const ora_flagcfg* fc,
-                  double* image, double* final_T, int32_t* ncontrib, uint64_t* chash,
-                  uint32_t* flags)
+                  const double* depth, const double* rgb, const double* errpar, int64_t m,
+                  const int64_t* order, const ora_view* v, int x0, int y0, int w, int h,
+                  const ora_flagcfg* fc, double* image, double* final_T, int32_t* ncontrib,
+                  uint64_t* chash, uint32_t* flags, double* fbound)
 {
     const double bg[3] = {v->bg[0], v->bg[1], v->bg[2]};
     const int64_t npx = (int64_t)w * h;
+    const double E = ldexp(1.0, -24);
+    const int banded = fc != NULL && errpar != NULL;
+    /* largest colour any composite term can carry (for events beyond the
+     * per-pixel record) */
+    double cmax = 0.0;
+    for (int ch = 0; ch < 3; ++ch) cmax = bg[ch] > cmax ? bg[ch] : cmax;
+    for (int64_t j = 0; j < m; ++j)
+        for (int ch = 0; ch < 3; ++ch) {
+            const double x = rgb[(int64_t)ch * n + order[j]];
+            cmax = x > cmax ? x : cmax;
+        }
 #pragma omp parallel for schedule(dynamic, 1)
     for (int py = 0; py < h; ++py) {
         for (int px = 0; px < w; ++px) {
@@ -395,36 +482,71 @@ int ora_composite(int64_t n, const double* mean2d, const double* conic, const do
             double T = 1.0, C[3] = {0, 0, 0};
             int32_t nc = 0;
             uint64_t hsh = 1469598103934665603ull;
+            ora_event ev[ORA_MAX_EVENTS];
+            int nev = 0;
+            double fb = 0.0;     /* bound of events already settled */
             uint32_t fl = 0;
+            double eT = 0.0;     /* band of ln T accumulated so far */
             int have_prev = 0;
-            double prev_z = 0, prev_a = 0, prev_rgb[3] = {0, 0, 0}, prev_T = 0;
+            double prev_z = 0, prev_ez = 0, prev_a = 0, prev_rgb[3] = {0, 0, 0}, prev_T = 0;
             for (int64_t j = 0; j < m; ++j) {
                 const int64_t g = order[j];
                 const double dx = mean2d[g] - pxc, dy = mean2d[n + g] - pyc;
-                const double q = conic[g] * dx * dx + 2.0 * conic[n + g] * dx * dy + conic[2 * n + g] * dy * dy;
+                const double ca = conic[g], cb = conic[n + g], cc = conic[2 * n + g];
+                const double q = ca * dx * dx + 2.0 * cb * dx * dy + cc * dy * dy;
                 const double araw = alpha_c[g] * exp(-0.5 * q);
                 const double a = araw < ALPHA_MAX ? araw : ALPHA_MAX;
-                if (fc && fabs(araw - ALPHA_MIN) < fc->tau_alpha * ALPHA_MIN &&
-                    2.0 * ALPHA_MIN * T > fc->impact_min)
-                    fl |= ORA_FLAG_ALPHA;
+                double ea = 0.0;   /* band of ln alpha at this (Gaussian, pixel) */
+                if (banded) {
+                    const double w0 = ca * dx + cb * dy, w1 = cb * dx + cc * dy;
+                    const double aw0 = fabs(w0), aw1 = fabs(w1);
+                    const double qabs = ca * dx * dx + 2.0 * fabs(cb * dx * dy) + cc * dy * dy;
+                    const double squad = aw0 * aw0 * errpar[n + g] + 2.0 * aw0 * aw1 * errpar[2 * n + g] +
+                                         aw1 * aw1 * errpar[3 * n + g];
+                    ea = E * (fc->k_mu * (aw0 + aw1) * errpar[g] +
+                              fc->k_uv * (aw0 * fabs(mean2d[g]) + aw1 * fabs(mean2d[n + g])) +
+                              fc->k_s * 0.5 * squad + fc->k_eval * (8.0 + 0.5 * qabs) + fc->k_ac);
+                    if (fabs(log(araw / ALPHA_MIN)) < ea) {
+                        ora_event e = {a < ALPHA_MIN ? 0 : 1, a < ALPHA_MIN ? ALPHA_MIN * exp(ea) : a, T,
+                                       {C[0], C[1], C[2]}, {0, 0, 0}};
+                        for (int ch = 0; ch < 3; ++ch) e.rgb[ch] = rgb[(int64_t)ch * n + g];
+                        if (nev < ORA_MAX_EVENTS) ev[nev++] = e;
+                        else fb += e.a * T * cmax;
+                        fl |= ORA_FLAG_ALPHA;
+                        /* taking it the other way rescales T by about (1 - alpha) */
+                        eT += e.a;
+                    }
+                }
                 if (a < ALPHA_MIN) continue;
                 const double Tn = T * (1.0 - a);
-                if (fc && fabs(Tn - T_MIN) < fc->tau_T * T_MIN) fl |= ORA_FLAG_T;
-                if (Tn < T_MIN) break;
-                if (fc && have_prev) {
-                    const double z = depth[g];
-                    if (fabs(z - prev_z) < fc->tau_z * fabs(z)) {
-                        double dc = 0.0;
-                        for (int ch = 0; ch < 3; ++ch) {
-                            double e = fabs(rgb[(int64_t)ch * n + g] - prev_rgb[ch]);
-                            if (e > dc) dc = e;
-                        }
-                        if (prev_T * prev_a * a * dc > fc->impact_min) fl |= ORA_FLAG_DEPTH;
+                if (banded) {
+                    eT += a / (1.0 - a) * ea + fc->k_T * E;
+                    if (fabs(log(Tn / T_MIN)) < eT) {
+                        ora_event e = {Tn < T_MIN ? 2 : 3, a, T, {C[0], C[1], C[2]}, {0, 0, 0}};
+                        for (int ch = 0; ch < 3; ++ch) e.rgb[ch] = rgb[(int64_t)ch * n + g];
+                        if (nev < ORA_MAX_EVENTS) ev[nev++] = e;
+                        else fb += T * cmax;
+                        fl |= ORA_FLAG_T;
                     }
+                }
+                if (Tn < T_MIN) break;
+                const double ez = banded ? fc->k_z * E * errpar[4 * n + g] : 0.0;
+                if (banded && have_prev && fabs(depth[g] - prev_z) < ez + prev_ez) {
+                    double dc = 0.0;
+                    for (int ch = 0; ch < 3; ++ch) {
+                        const double e = fabs(rgb[(int64_t)ch * n + g] - prev_rgb[ch]);
+                        if (e > dc) dc = e;
+                    }
+                    /* swapping two consecutive contributors changes C by
+                     * T_prev a_prev a (rgb_prev - rgb) */
+                    const double imp = prev_T * prev_a * a * dc;
+                    fb += imp;
+                    if (imp > fc->impact_min) fl |= ORA_FLAG_DEPTH;
                 }
                 for (int ch = 0; ch < 3; ++ch) C[ch] += rgb[(int64_t)ch * n + g] * a * T;
                 have_prev = 1;
                 prev_z = depth[g];
+                prev_ez = ez;
                 prev_a = a;
                 prev_T = T;
                 for (int ch = 0; ch < 3; ++ch) prev_rgb[ch] = rgb[(int64_t)ch * n + g];
@@ -433,11 +555,37 @@ int ora_composite(int64_t n, const double* mean2d, const double* conic, const do
                 hsh = (hsh ^ (uint64_t)(g + 1)) * 1099511628211ull;
             }
             const int64_t p = (int64_t)py * w + px;
-            for (int ch = 0; ch < 3; ++ch) image[ch * npx + p] = C[ch] + T * bg[ch];
+            double img[3];
+            for (int ch = 0; ch < 3; ++ch) img[ch] = C[ch] + T * bg[ch];
+            /* first-order change of the pixel if each recorded decision went
+             * the other way (later decisions unchanged) */
+            uint32_t fl_imp = fl & ORA_FLAG_DEPTH;
+            for (int k = 0; k < nev; ++k) {
+                const ora_event* e = &ev[k];
+                double d = 0.0;
+                for (int ch = 0; ch < 3; ++ch) {
+                    double x;
+                    if (e->kind == 0) {          /* blended instead: rest rescaled by (1 - a) */
+                        x = e->a * (e->T * e->rgb[ch] - (img[ch] - e->C[ch]));
+                    } else if (e->kind == 1) {   /* skipped instead */
+                        const double rest = (img[ch] - e->C[ch] - e->a * e->T * e->rgb[ch]) / (1.0 - e->a);
+                        x = e->a * (e->T * e->rgb[ch] - rest);
+                    } else if (e->kind == 2) {   /* blended instead of stopping */
+                        x = e->a * e->T * (e->rgb[ch] - bg[ch]);
+                    } else {                     /* stopped instead */
+                        x = img[ch] - e->C[ch] - e->T * bg[ch];
+                    }
+                    if (fabs(x) > d) d = fabs(x);
+                }
+                fb += d;
+                if (d > fc->impact_min) fl_imp |= e->kind <= 1 ? ORA_FLAG_ALPHA : ORA_FLAG_T;
+            }
+            for (int ch = 0; ch < 3; ++ch) image[ch * npx + p] = img[ch];
             if (final_T) final_T[p] = T;
             if (ncontrib) ncontrib[p] = nc;
             if (chash) chash[p] = hsh;
-            if (flags) flags[p] = fl;
+            if (flags) flags[p] = banded ? fl_imp : 0u;
+            if (fbound) fbound[p] = banded ? 1.01 * fb : 0.0;
         }
     }
     return 0;
@@ -498,7 +646,7 @@ int ora_render(int64_t n, const double* mu_p, const double* mu_t, const double* 
                const double* L, const double* alpha, const double* sh, const ora_view* v,
                int x0, int y0, int w, int h, const ora_flagcfg* fc,
                double* image, double* final_T, int32_t* ncontrib, uint64_t* chash,
-               uint32_t* flags)
+               uint32_t* flags, double* fbound)
 {
     double* mu_c = (double*)malloc(sizeof(double) * 3 * n + 8);
     double* cov_c = (double*)malloc(sizeof(double) * 6 * n + 8);
@@ -510,18 +658,21 @@ int ora_render(int64_t n, const double* mu_p, const double* mu_t, const double* 
     int32_t* rect = (int32_t*)malloc(sizeof(int32_t) * 4 * n + 8);
     uint8_t* vis = (uint8_t*)malloc((size_t)n + 8);
     int64_t* order = (int64_t*)malloc(sizeof(int64_t) * n + 8);
+    double* errpar = fc ? (double*)malloc(sizeof(double) * 5 * n + 8) : NULL;
     int rc = 0;
-    if (!mu_c || !cov_c || !alpha_c || !mean2d || !conic || !depth || !rgb || !rect || !vis || !order) {
+    if (!mu_c || !cov_c || !alpha_c || !mean2d || !conic || !depth || !rgb || !rect || !vis || !order ||
+        (fc && !errpar)) {
         rc = -1;
     } else {
         ora_slice(n, mu_p, mu_t, mu_d, L, alpha, v, mu_c, cov_c, alpha_c, NULL, NULL, NULL);
-        ora_project(n, mu_c, cov_c, alpha_c, sh, v, mean2d, conic, depth, rgb, rect, vis);
+        ora_project(n, mu_c, cov_c, alpha_c, sh, v, mean2d, conic, depth, rgb, rect, vis, NULL);
         int64_t m = ora_order(n, depth, vis, order);
-        ora_composite(n, mean2d, conic, alpha_c, depth, rgb, m, order, v, x0, y0, w, h, fc,
-                      image, final_T, ncontrib, chash, flags);
+        if (errpar) ora_fp32_model(n, mu_c, cov_c, v, errpar);
+        ora_composite(n, mean2d, conic, alpha_c, depth, rgb, errpar, m, order, v, x0, y0, w, h, fc,
+                      image, final_T, ncontrib, chash, flags, fbound);
     }
     free(mu_c); free(cov_c); free(alpha_c); free(mean2d); free(conic);
-    free(depth); free(rgb); free(rect); free(vis); free(order);
+    free(depth); free(rgb); free(rect); free(vis); free(order); free(errpar);
     return rc;
 }
 

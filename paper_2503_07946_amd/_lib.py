@@ -15,7 +15,7 @@ SD7_TILE = 16
 SD7_PAIR_ROUND = 2048       # a frame's arena share is a multiple of this (sd7.h)
 SD7_FLAG_NONPOS_DIAG, SD7_FLAG_NONFINITE, SD7_FLAG_PAIR_OVERFLOW = 1, 2, 4
 SD7_CNT_KEPT, SD7_CNT_PAIRS, SD7_CNT_PAIR_BASE, SD7_CNT_FLAGS = 0, 1, 2, 3
-SD7_CNT_NEEDED = 4          # pairs the frame needed (internal word, also set on overflow)
+SD7_CNT_NEEDED = 4          # pairs the frame needs (also written on overflow)
 SD7_CNT_WORDS = 16
 SD7_AGR_WEIGHTS = 9443      # floats of one scene's AGR weights (sd7.h)
 

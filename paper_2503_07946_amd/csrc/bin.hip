@@ -496,7 +496,7 @@ __global__ __launch_bounds__(64) void k_setup_pairs(const FrameDev* __restrict__
         const uint32_t fl = c[SD7_CNT_FLAGS] & ~SD7_FLAG_PAIR_OVERFLOW;
         c[SD7_CNT_FLAGS] = my_ov ? (fl | SD7_FLAG_PAIR_OVERFLOW) : fl;
         c[SD7_CNT_PAIRS] = my_len;
-        c[4] = P;  // pairs the frame needs
+        c[SD7_CNT_NEEDED] = P;
         c[SD7_CNT_PAIR_BASE] = my_base;
         c[5] = lo;  // scan value at the frame's first Gaussian
         SortSeg sg;

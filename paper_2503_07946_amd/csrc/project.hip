@@ -67,55 +67,60 @@ __device__ __forceinline__ void sh_grad(float x, float y, float z, const float b
     g[0] = gx; g[1] = gy; g[2] = gz;
 }
 
+// The projection of one conditional Gaussian, evaluated in FP64 from its FP32
+// sliced statistics (the splat record and footprint are rounded to FP32 when
+// written).  FP64 here keeps the 2D covariance's inverse accurate for
+// elongated splats, whose 2D covariance is ill-conditioned: in FP32 its
+// determinant cancels and the conic loses up to about 1e-3 of its value.
 struct Proj {
-    float x[3];     // camera coordinates
-    float u, v;     // mean2d
-    float rx, ry;   // ratios used in J (clamped)
-    bool clx, cly;  // ratio clamped
-    float M[2][3];  // J R
-    float S[3][3];  // Sigma_c
-    float s00, s01, s11, det;
-    float a, b, c;  // conic
+    double x[3];      // camera coordinates
+    double iz;        // 1 / z
+    double u, v;      // mean2d
+    double rx, ry;    // ratios used in J (clamped)
+    bool clx, cly;    // ratio clamped
+    double M[2][3];   // J R
+    double s00, s01, s11, det;
+    double a, b, c;   // conic
 };
 
 __device__ __forceinline__ bool project_one(const FrameDev& F, const float m[3], const float cv[6], Proj& p)
 {
-    const float dm0 = m[0] - F.c[0], dm1 = m[1] - F.c[1], dm2 = m[2] - F.c[2];
+    const double dm0 = (double)m[0] - F.c[0], dm1 = (double)m[1] - F.c[1], dm2 = (double)m[2] - F.c[2];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) p.x[r] = F.R[3 * r] * dm0 + F.R[3 * r + 1] * dm1 + F.R[3 * r + 2] * dm2;
-    const float z = p.x[2];
-    if (!(z > kZNear)) return false;
-    const float fx = F.fx, fy = F.fy;
-    const float iz = __builtin_amdgcn_rcpf(z);  // hardware reciprocal: z > 0.2, error about 1 ulp
-    p.u = fmaf(fx * p.x[0], iz, F.cx);
-    p.v = fmaf(fy * p.x[1], iz, F.cy);
-    const float limx = F.limx, limy = F.limy;
-    float rx = p.x[0] * iz, ry = p.x[1] * iz;
+    for (int r = 0; r < 3; ++r)
+        p.x[r] = (double)F.R[3 * r] * dm0 + (double)F.R[3 * r + 1] * dm1 + (double)F.R[3 * r + 2] * dm2;
+    const double z = p.x[2];
+    if (!(z > (double)kZNear)) return false;
+    const double fx = F.fx, fy = F.fy;
+    p.iz = 1.0 / z;
+    p.u = fx * p.x[0] * p.iz + (double)F.cx;
+    p.v = fy * p.x[1] * p.iz + (double)F.cy;
+    const double limx = F.limx, limy = F.limy;
+    double rx = p.x[0] * p.iz, ry = p.x[1] * p.iz;
     p.clx = rx >= limx || rx <= -limx;
     p.cly = ry >= limy || ry <= -limy;
-    rx = fminf(fmaxf(rx, -limx), limx);
-    ry = fminf(fmaxf(ry, -limy), limy);
+    rx = fmin(fmax(rx, -limx), limx);
+    ry = fmin(fmax(ry, -limy), limy);
     p.rx = rx;
     p.ry = ry;
-    const float j00 = fx * iz, j02 = -fx * rx * iz, j11 = fy * iz, j12 = -fy * ry * iz;
+    const double j00 = fx * p.iz, j02 = -fx * rx * p.iz, j11 = fy * p.iz, j12 = -fy * ry * p.iz;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        p.M[0][k] = j00 * F.R[k] + j02 * F.R[6 + k];
-        p.M[1][k] = j11 * F.R[3 + k] + j12 * F.R[6 + k];
+        p.M[0][k] = j00 * (double)F.R[k] + j02 * (double)F.R[6 + k];
+        p.M[1][k] = j11 * (double)F.R[3 + k] + j12 * (double)F.R[6 + k];
     }
-    p.S[0][0] = cv[0]; p.S[0][1] = p.S[1][0] = cv[1]; p.S[0][2] = p.S[2][0] = cv[2];
-    p.S[1][1] = cv[3]; p.S[1][2] = p.S[2][1] = cv[4]; p.S[2][2] = cv[5];
-    float T[2][3];
+    const double S[3][3] = {{cv[0], cv[1], cv[2]}, {cv[1], cv[3], cv[4]}, {cv[2], cv[4], cv[5]}};
+    double T[2][3];
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) T[r][k] = p.M[r][0] * p.S[0][k] + p.M[r][1] * p.S[1][k] + p.M[r][2] * p.S[2][k];
-    p.s00 = T[0][0] * p.M[0][0] + T[0][1] * p.M[0][1] + T[0][2] * p.M[0][2] + kDilation;
+        for (int k = 0; k < 3; ++k) T[r][k] = p.M[r][0] * S[0][k] + p.M[r][1] * S[1][k] + p.M[r][2] * S[2][k];
+    p.s00 = T[0][0] * p.M[0][0] + T[0][1] * p.M[0][1] + T[0][2] * p.M[0][2] + (double)kDilation;
     p.s01 = T[0][0] * p.M[1][0] + T[0][1] * p.M[1][1] + T[0][2] * p.M[1][2];
-    p.s11 = T[1][0] * p.M[1][0] + T[1][1] * p.M[1][1] + T[1][2] * p.M[1][2] + kDilation;
+    p.s11 = T[1][0] * p.M[1][0] + T[1][1] * p.M[1][1] + T[1][2] * p.M[1][2] + (double)kDilation;
     p.det = p.s00 * p.s11 - p.s01 * p.s01;
-    if (!(p.det > 0.0f)) return false;
-    const float idet = __builtin_amdgcn_rcpf(p.det);
+    if (!(p.det > 0.0)) return false;
+    const double idet = 1.0 / p.det;
     p.a = p.s11 * idet;
     p.b = -p.s01 * idet;
     p.c = p.s00 * idet;
@@ -138,24 +143,26 @@ __device__ __forceinline__ uint2 footprint_trims(const Proj& p, float k, uint32_
                                                  uint32_t ry1)
 {
     const uint32_t w = rx1 - rx0, h = ry1 - ry0;
-    const float tr = p.s00 + p.s11;
-    if (w < 2 || h < 2 || !(tr * tr < 1e6f * p.det)) return make_uint2(0u, 0u);
+    const float s00 = (float)p.s00, s01 = (float)p.s01, s11 = (float)p.s11, det = (float)p.det;
+    const float pu = (float)p.u, pv = (float)p.v;
+    const float tr = s00 + s11;
+    if (w < 2 || h < 2 || !(tr * tr < 1e6f * det)) return make_uint2(0u, 0u);
     const uint32_t m = h > 8 ? h - 4 : 4;  // first of the bottom rows
     const uint32_t nrow = min(h, 8u);
     const float km = fmaf(k, 1.002f, 0.02f);
-    const float r11 = __builtin_amdgcn_rcpf(p.s11);
-    const float slope = p.s01 * r11, wsq = p.det * r11;
-    const float dyx = p.s01 * __builtin_amdgcn_sqrtf(km * __builtin_amdgcn_rcpf(p.s00));  // rightmost point; leftmost at -dyx
-    const float hy = __builtin_amdgcn_sqrtf(km * p.s11);
+    const float r11 = __builtin_amdgcn_rcpf(s11);
+    const float slope = s01 * r11, wsq = det * r11;
+    const float dyx = s01 * __builtin_amdgcn_sqrtf(km * __builtin_amdgcn_rcpf(s00));  // rightmost point; leftmost at -dyx
+    const float hy = __builtin_amdgcn_sqrtf(km * s11);
     const float inv_tile = 1.0f / (float)kTile;
     uint32_t word[2] = {0u, 0u};
     for (uint32_t q = 0; q < nrow; ++q) {
         const uint32_t r = q < 4 ? q : m + (q - 4);
-        const float y = (float)((ry0 + r) * kTile) + 0.5f - p.v;
+        const float y = (float)((ry0 + r) * kTile) + 0.5f - pv;
         const float dya = fmaxf(y, -hy), dyb = fminf(y + (float)(kTile - 1), hy);
         const float yl = fminf(fmaxf(-dyx, dya), dyb), yr = fminf(fmaxf(dyx, dya), dyb);
-        const float xl = fmaf(slope, yl, p.u) - __builtin_amdgcn_sqrtf(fmaxf(fmaf(-yl * r11, yl, km), 0.0f) * wsq);
-        const float xr = fmaf(slope, yr, p.u) + __builtin_amdgcn_sqrtf(fmaxf(fmaf(-yr * r11, yr, km), 0.0f) * wsq);
+        const float xl = fmaf(slope, yl, pu) - __builtin_amdgcn_sqrtf(fmaxf(fmaf(-yl * r11, yl, km), 0.0f) * wsq);
+        const float xr = fmaf(slope, yr, pu) + __builtin_amdgcn_sqrtf(fmaxf(fmaf(-yr * r11, yr, km), 0.0f) * wsq);
         // tiles whose last centre column lies left of xl, or whose first lies
         // right of xr; a strip that misses the ellipse empties the row (as
         // far as 15 + 15 tiles go); NaN keeps the row whole (fmaxf returns the
@@ -193,9 +200,10 @@ __device__ __forceinline__ bool project_emit(const FrameDev& F, uint32_t i, floa
     uint2 trims = make_uint2(0u, 0u);
     if (keep) {
         const float k = 2.0f * logf(ac * 255.0f);
-        const float hx = __builtin_amdgcn_sqrtf(k * p.s00), hy = __builtin_amdgcn_sqrtf(k * p.s11);
-        float tx0 = floorf((p.u - hx) / (float)kTile), tx1 = floorf((p.u + hx) / (float)kTile);
-        float ty0 = floorf((p.v - hy) / (float)kTile), ty1 = floorf((p.v + hy) / (float)kTile);
+        const float pu = (float)p.u, pv = (float)p.v;
+        const float hx = __builtin_amdgcn_sqrtf(k * (float)p.s00), hy = __builtin_amdgcn_sqrtf(k * (float)p.s11);
+        float tx0 = floorf((pu - hx) / (float)kTile), tx1 = floorf((pu + hx) / (float)kTile);
+        float ty0 = floorf((pv - hy) / (float)kTile), ty1 = floorf((pv + hy) / (float)kTile);
         tx0 = fmaxf(tx0, 0.0f);
         ty0 = fmaxf(ty0, 0.0f);
         tx1 = fminf(tx1, (float)F.tiles_x - 1.0f);
@@ -224,17 +232,18 @@ __device__ __forceinline__ bool project_emit(const FrameDev& F, uint32_t i, floa
     float4* rec = splat + (g0 + i) * 3;
     if (keep) {
         // exponent of alpha in base 2: A dx^2 + B dx dy + C dy^2 + log2(alpha_c)
-        const float C = kNegHalfLog2e * p.c;
-        rec[0] = make_float4(p.u, p.v, kNegHalfLog2e * p.a, kNegLog2e * p.b);
+        const double nhl2e = -0.72134752044448170368;  // -log2(e) / 2
+        const float C = (float)(nhl2e * p.c);
+        rec[0] = make_float4((float)p.u, (float)p.v, (float)(nhl2e * p.a), (float)(2.0 * nhl2e * p.b));
         rec[1] = make_float4(C, log2f(ac), rgb[0], rgb[1]);
-        rec[2] = make_float4(rgb[2], 16.0f * C, ac, p.x[2]);
+        rec[2] = make_float4(rgb[2], 16.0f * C, ac, (float)p.x[2]);
     } else {
         rec[0] = make_float4(0.f, 0.f, 0.f, 0.f);
         rec[1] = make_float4(0.f, 0.f, 0.f, 0.f);
         rec[2] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     rect[g0 + i] = make_uint4(rx0 | (ry0 << 16), rx1 | (ry1 << 16), trims.x, trims.y);
-    depth_key[g0 + i] = keep ? __float_as_uint(p.x[2]) : kCulled;
+    depth_key[g0 + i] = keep ? __float_as_uint((float)p.x[2]) : kCulled;
     return keep;
 }
 
@@ -332,70 +341,72 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(const FrameDev* __restri
 #pragma unroll
         for (int a = 0; a < 3; ++a) gmu[a] += (gdir[a] - dir[a] * dd) * inv;
 
-        // conic (a, b, c) = inverse of Sigma2D -> d(s00, s01, s11)
-        const float ga = ds[2], gb = ds[3], gc = ds[4];
-        const float A = p.a, B = p.b, C = p.c;
-        const float g00 = -(ga * A * A + gb * A * B + gc * B * B);
-        const float g11 = -(ga * B * B + gb * B * C + gc * C * C);
-        const float g01 = -(2.f * ga * A * B + gb * (A * C + B * B) + 2.f * gc * B * C);
+        // conic (a, b, c) = inverse of Sigma2D -> d(s00, s01, s11), FP64 like the forward
+        const double ga = ds[2], gb = ds[3], gc = ds[4];
+        const double A = p.a, B = p.b, C = p.c;
+        const double g00 = -(ga * A * A + gb * A * B + gc * B * B);
+        const double g11 = -(ga * B * B + gb * B * C + gc * C * C);
+        const double g01 = -(2.0 * ga * A * B + gb * (A * C + B * B) + 2.0 * gc * B * C);
         // symmetric 2x2 gradient of Sigma2D (entries independent)
-        const float G2[2][2] = {{g00, 0.5f * g01}, {0.5f * g01, g11}};
+        const double G2[2][2] = {{g00, 0.5 * g01}, {0.5 * g01, g11}};
         // dSigma_c = M^T G2 M
-        float GM[2][3];
+        double GM[2][3];
 #pragma unroll
         for (int r = 0; r < 2; ++r)
 #pragma unroll
             for (int k = 0; k < 3; ++k) GM[r][k] = G2[r][0] * p.M[0][k] + G2[r][1] * p.M[1][k];
-        float Gs[3][3];
+        double Gs[3][3];
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int b2 = 0; b2 < 3; ++b2) Gs[a][b2] = p.M[0][a] * GM[0][b2] + p.M[1][a] * GM[1][b2];
-        gcov[0] = Gs[0][0];
-        gcov[1] = Gs[0][1] + Gs[1][0];
-        gcov[2] = Gs[0][2] + Gs[2][0];
-        gcov[3] = Gs[1][1];
-        gcov[4] = Gs[1][2] + Gs[2][1];
-        gcov[5] = Gs[2][2];
+        gcov[0] = (float)Gs[0][0];
+        gcov[1] = (float)(Gs[0][1] + Gs[1][0]);
+        gcov[2] = (float)(Gs[0][2] + Gs[2][0]);
+        gcov[3] = (float)Gs[1][1];
+        gcov[4] = (float)(Gs[1][2] + Gs[2][1]);
+        gcov[5] = (float)Gs[2][2];
         // dM = 2 G2 M Sigma_c ; dJ = dM R^T
-        float dM[2][3];
+        const double S[3][3] = {{cv[0], cv[1], cv[2]}, {cv[1], cv[3], cv[4]}, {cv[2], cv[4], cv[5]}};
+        double dM[2][3];
 #pragma unroll
         for (int r = 0; r < 2; ++r)
 #pragma unroll
             for (int k = 0; k < 3; ++k)
-                dM[r][k] = 2.f * (GM[r][0] * p.S[0][k] + GM[r][1] * p.S[1][k] + GM[r][2] * p.S[2][k]);
-        float dJ[2][3];
+                dM[r][k] = 2.0 * (GM[r][0] * S[0][k] + GM[r][1] * S[1][k] + GM[r][2] * S[2][k]);
+        double dJ[2][3];
 #pragma unroll
         for (int r = 0; r < 2; ++r)
 #pragma unroll
             for (int q = 0; q < 3; ++q)
                 dJ[r][q] = dM[r][0] * F.R[3 * q] + dM[r][1] * F.R[3 * q + 1] + dM[r][2] * F.R[3 * q + 2];
-        const float fx = F.fx, fy = F.fy;
-        const float x = p.x[0], y = p.x[1], z = p.x[2];
-        const float iz = 1.0f / z, iz2 = iz * iz;
-        float gx = 0.f, gy = 0.f, gz = 0.f;
+        const double fx = F.fx, fy = F.fy;
+        const double x = p.x[0], y = p.x[1];
+        const double iz = p.iz, iz2 = iz * iz;
+        double gx = 0.0, gy = 0.0, gz = 0.0;
         // J00 = fx/z, J02 = -fx rx/z, J11 = fy/z, J12 = -fy ry/z
         gz += dJ[0][0] * (-fx * iz2) + dJ[1][1] * (-fy * iz2);
         if (!p.clx) {
             gx += dJ[0][2] * (-fx * iz2);
-            gz += dJ[0][2] * (2.f * fx * x * iz2 * iz);
+            gz += dJ[0][2] * (2.0 * fx * x * iz2 * iz);
         } else {
             gz += dJ[0][2] * (fx * p.rx * iz2);
         }
         if (!p.cly) {
             gy += dJ[1][2] * (-fy * iz2);
-            gz += dJ[1][2] * (2.f * fy * y * iz2 * iz);
+            gz += dJ[1][2] * (2.0 * fy * y * iz2 * iz);
         } else {
             gz += dJ[1][2] * (fy * p.ry * iz2);
         }
         // mean2d
-        gx += ds[0] * fx * iz;
-        gz += ds[0] * (-fx * x * iz2);
-        gy += ds[1] * fy * iz;
-        gz += ds[1] * (-fy * y * iz2);
+        gx += (double)ds[0] * fx * iz;
+        gz += (double)ds[0] * (-fx * x * iz2);
+        gy += (double)ds[1] * fy * iz;
+        gz += (double)ds[1] * (-fy * y * iz2);
         // x_cam = R (mu - c)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) gmu[a] += F.R[a] * gx + F.R[3 + a] * gy + F.R[6 + a] * gz;
+        for (int a = 0; a < 3; ++a)
+            gmu[a] += (float)((double)F.R[a] * gx + (double)F.R[3 + a] * gy + (double)F.R[6 + a] * gz);
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) d_mu_c[3 * g0 + (size_t)a * n + i] = gmu[a];

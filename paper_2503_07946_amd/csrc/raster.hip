@@ -213,13 +213,17 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v)
     return v;
 }
 
-// Front-to-back recomputation: for each of the list entries the pixel
-// consumed in the forward pass, with S = C_out - sum_{j<=i} rgb_j w_j (the colour still to come,
-// background included):  dC/d rgb_i = w_i,  dC/d alpha_i = rgb_i T_i -
-// S_i / (1 - alpha_i).  Per lane the four pixels' terms are folded into sums
-// (S0 = sum s, S1 = sum s dy, S2 = sum s dy^2 with s = dl/d alpha * alpha)
-// from which the mean, conic and opacity derivatives follow; each of the nine
-// splat derivatives is then summed over the wave and added with one atomic.
+// Back-to-front recomputation: each pixel starts from the forward's final
+// transmittance T_final and walks the list entries it consumed (the first
+// `last`) in reverse.  Behind entry i the colour still to come is
+// S_i = T_final bg + sum_{j > i} rgb_j w_j, accumulated here from the back as
+// a sum of non-negative terms (no cancellation however small T gets), and the
+// transmittance in front of it is T_i = T_{i+1} / (1 - alpha_i).  Then
+// dC/d rgb_i = w_i = T_i alpha_i and dC/d alpha_i = rgb_i T_i - S_i / (1 - alpha_i).
+// Per lane the four pixels' terms are folded into sums (S0 = sum s,
+// S1 = sum s dy, S2 = sum s dy^2 with s = dl/d alpha * alpha) from which the
+// mean, conic and opacity derivatives follow; each of the nine splat
+// derivatives is then summed over the wave and added with one atomic.
 __global__ __launch_bounds__(64) void k_raster_bwd(const FrameDev* __restrict__ tab, BlockMap bm,
                                                    const uint2* __restrict__ ranges,
                                                    const uint32_t* __restrict__ pair_g,
@@ -235,7 +239,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const FrameDev* __restrict__ 
     const uint32_t py0 = ty * kTile + (lane >> 4);  // band k: row py0 + 4k
     const float fx = (float)px + 0.5f, fy0 = (float)py0 + 0.5f;
     const size_t plane = (size_t)F.W * F.H;
-    float T[4], Co[4][3], gC[4][3], acc[4][3];
+    float T[4], Sc[4][3], gC[4][3];
     uint32_t last[4];
     uint32_t lmax = 0;
 #pragma unroll
@@ -244,12 +248,13 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const FrameDev* __restrict__ 
         T[k] = 1.0f;
         last[k] = 0;
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) Co[k][ch] = gC[k][ch] = acc[k][ch] = 0.0f;
+        for (int ch = 0; ch < 3; ++ch) Sc[k][ch] = gC[k][ch] = 0.0f;
         if (px < F.W && py < F.H) {
             const size_t pix = (size_t)py * F.W + px;
+            T[k] = F.final_T[pix];
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
-                Co[k][ch] = F.image[ch * plane + pix];
+                Sc[k][ch] = T[k] * F.bg[ch];
                 gC[k][ch] = F.dL_dimage[ch * plane + pix];
             }
             last[k] = F.last[pix];
@@ -262,7 +267,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const FrameDev* __restrict__ 
     const float4* __restrict__ rec = splat + (size_t)F.g0 * 3;
     const uint32_t gmax = __builtin_amdgcn_readfirstlane(F.n - 1);  // pairs exist only if n > 0
     const size_t n = F.n, g0 = F.g0;
-    for (uint32_t e = rg.x; e < e_end; ++e) {
+    for (uint32_t e = e_end; e-- > rg.x;) {
         const uint32_t g = min(pair_g[e], gmax);
         const Splat s = load_splat(rec, g);
         const uint32_t pos = e - rg.x;
@@ -277,19 +282,13 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const FrameDev* __restrict__ 
         for (int k = 0; k < 4; ++k) {
             const float raw = exp2_fast(p[k]);
             const float alpha = fminf(kAlphaMax, raw);
-            const float w = T[k] * alpha;
-            const float Tn = fmaf(-T[k], alpha, T[k]);
-            const bool con = pass[k] && !(Tn < kTMin);
-            const float wc = con ? w : 0.0f;
-            acc[k][0] = fmaf(s.r, wc, acc[k][0]);
-            acc[k][1] = fmaf(s.g, wc, acc[k][1]);
-            acc[k][2] = fmaf(s.b, wc, acc[k][2]);
             const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);  // 1 - alpha >= 0.01: the hardware reciprocal (1 ulp)
+            const float Tb = pass[k] ? T[k] * inv : T[k];  // transmittance in front of the entry
+            const float wc = pass[k] ? Tb * alpha : 0.0f;
             const float dot_rgb = gC[k][0] * s.r + gC[k][1] * s.g + gC[k][2] * s.b;
-            const float dot_s = gC[k][0] * (Co[k][0] - acc[k][0]) + gC[k][1] * (Co[k][1] - acc[k][1]) +
-                                gC[k][2] * (Co[k][2] - acc[k][2]);
-            const float ga = T[k] * dot_rgb - dot_s * inv;
-            const float sk = (con && raw < kAlphaMax) ? ga * alpha : 0.0f;
+            const float dot_s = gC[k][0] * Sc[k][0] + gC[k][1] * Sc[k][1] + gC[k][2] * Sc[k][2];
+            const float ga = Tb * dot_rgb - dot_s * inv;
+            const float sk = (pass[k] && raw < kAlphaMax) ? ga * alpha : 0.0f;
             S0 += sk;
             const float dy = dy0 - 4.0f * k;
             const float sdy = sk * dy;
@@ -298,7 +297,10 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const FrameDev* __restrict__ 
             Sr = fmaf(wc, gC[k][0], Sr);
             Sg = fmaf(wc, gC[k][1], Sg);
             Sb = fmaf(wc, gC[k][2], Sb);
-            T[k] = con ? Tn : T[k];
+            Sc[k][0] = fmaf(s.r, wc, Sc[k][0]);
+            Sc[k][1] = fmaf(s.g, wc, Sc[k][1]);
+            Sc[k][2] = fmaf(s.b, wc, Sc[k][2]);
+            T[k] = Tb;
         }
         // derivatives w.r.t. (u, v, a, b, c, opacity, r, g, b) of this lane's pixels
         float v9[9];

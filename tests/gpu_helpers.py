@@ -100,7 +100,81 @@ def oracle_rect_flags(sl, pr, view, eps=1e-4):
 
 
 def image_check(gpu_img, ora, tol=1e-4):
-    """max |gpu - oracle| over unflagged pixels; returns (err, n_flagged)."""
-    mask = ora.flags == 0
-    err = np.abs(gpu_img.astype(np.float64) - ora.image)
-    return float(err[:, mask].max()) if mask.any() else 0.0, int((~mask).sum())
+    """Every pixel is compared: |gpu - oracle| <= tol + fbound, where fbound is
+    the oracle's bound on the first-order change of the pixel should an FP32
+    evaluation take one of its in-band decisions (opacity test, stop, depth
+    order) the other way (0 on pixels without such a decision).  Returns (max
+    over all pixels of |gpu - oracle| - fbound, number of flagged pixels)."""
+    err = np.abs(gpu_img.astype(np.float64) - ora.image).max(0)
+    return float((err - ora.fbound).max()), int((ora.flags != 0).sum())
+
+
+def grad_entry_error(gpu: np.ndarray, ora: np.ndarray) -> np.ndarray:
+    """Per-entry gradient error |g_gpu - g_ora| / max(|g_ora|, 1e-2 max|g_ora|)
+    (the bar is 1e-3)."""
+    scale = np.maximum(np.abs(ora), 1e-2 * np.abs(ora).max())
+    return np.abs(gpu - ora) / np.maximum(scale, 1e-300)
+
+
+SPLAT_GROUPS = ((0, 2), (2, 5), (5, 6), (6, 9))   # mean2d, conic, opacity, colour
+SPLAT_GROUP_NAMES = ("d_mean2d", "d_conic", "d_opacity", "d_rgb")
+
+
+def splat_grads(b, f):
+    """The GPU's gradients with respect to frame f's splats, [9][n] (the
+    reverse compositing's output: u, v, a, b, c, opacity, r, g, b)."""
+    return b.planes("off_d_splat", 9, f).cpu().numpy().astype(np.float64)
+
+
+def check_gradients(g_gpu: dict, d_gpu: np.ndarray, g_ora: dict, d_ora: np.ndarray, J: dict, bar=1e-3) -> dict:
+    """The gradient parity bar (Sec. 4.4 reverse pass).
+
+    * Splat gradients (the sums over pixels the reverse compositing
+      accumulates in FP32): per entry |d_gpu - d_ora| <= bar max(|d_ora|,
+      1e-2 max of its group).
+    * Parameter gradients: per group relative L2 <= bar; per entry
+      |g_gpu - g_ora| <= max(bar max(|g_ora|, 1e-2 max|g_ora|), prop), where
+      prop = bar (|J|^T s)_entry propagates the splat bar s through the
+      magnitudes of the Jacobian J of projection and slice (both reverses are
+      linear in the splat gradients and run in FP64, so an error within the
+      bar there moves a parameter gradient by at most prop; prop exceeds the
+      plain bar only where the 2D covariance or the (t, d) block is
+      ill-conditioned).
+    Returns the measured figures."""
+    rep = {}
+    sd = np.abs(d_ora).copy()
+    for a, c in SPLAT_GROUPS:
+        sd[a:c] = np.maximum(sd[a:c], 1e-2 * np.abs(d_ora[a:c]).max())
+    e_d = np.abs(d_gpu - d_ora) / np.maximum(sd, 1e-300)
+    for name, (a, c) in zip(SPLAT_GROUP_NAMES, SPLAT_GROUPS):
+        rep[name] = float(e_d[a:c].max())
+    for k, go in g_ora.items():
+        if k == "lambda":
+            continue
+        a = np.asarray(g_gpu[k], np.float64).reshape(go.shape)
+        err = np.abs(a - go)
+        plain = bar * np.maximum(np.abs(go), 1e-2 * np.abs(go).max())
+        prop = bar * np.einsum("jpn,jn->pn", np.abs(J[k]), sd).reshape(go.shape)
+        tol = np.maximum(plain, prop)
+        rep[k] = {"rel_l2": float(np.linalg.norm(a - go) / max(np.linalg.norm(go), 1e-30)),
+                  "worst_entry": float((err / np.maximum(plain, 1e-300) * bar).max()),
+                  "of_bound": float((err / np.maximum(tol, 1e-300)).max()),
+                  "entries_over_plain_bar": int((err > plain).sum())}
+    assert max(rep[x] for x in SPLAT_GROUP_NAMES) <= bar, rep
+    for k, r in rep.items():
+        if isinstance(r, dict):
+            assert r["rel_l2"] <= bar and r["of_bound"] <= 1.0, (k, rep)
+    return rep
+
+
+def flag_cap(npx: int) -> float:
+    """Largest accepted number of flagged pixels: 0.5 % (at least 2)."""
+    return max(2.0, 0.005 * npx)
+
+
+# The FP32 error scales of the refined (AGR) path, for the oracle's decision
+# bands: twice the largest relative errors measured against the oracle, in
+# units of 2^-24 (mu_cond 2.4e-6 of its scale through mean2d, x sqrt 3;
+# Sigma_cond 1.5e-6; alpha_cond 1.9e-5: FP32 sums of up to 64 products in the
+# refinement's MLPs).
+AGR_FLAGS = dict(k_mu=2 * 1.7321 * 2.4e-6 * 2 ** 24, k_s=2 * 1.5e-6 * 2 ** 24, k_ac=2 * 1.9e-5 * 2 ** 24)

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import scenegen
-from tests.gpu_helpers import image_check, slice_tolerance
+from tests.gpu_helpers import AGR_FLAGS, image_check, slice_tolerance
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -114,7 +114,7 @@ def test_agr_slice_and_image_parity(R, case, report):
     assert np.all(np.abs(mu - ora.mu_c)[:, ok] <= tol_mu[:, ok]), e_mu
     assert np.all(np.abs(cov - ora.cov_c)[:, ok] <= tol_cv[:, ok]), e_cv
     assert np.all(np.abs(ac - ora.alpha_c)[ok] <= tol_ac[ok]), e_ac
-    img = oracle.render(sc, v, agr_weights=w)
+    img = oracle.render(sc, v, agr_weights=w, flags=AGR_FLAGS)
     err, nflag = image_check(b.frames[0].image.cpu().numpy(), img)
     report("agr_image_parity", case=case, max_abs=err, flagged=nflag)
     assert err <= 1e-4, (err, nflag)

@@ -6,6 +6,7 @@ import pytest
 import oracle
 import oracle.grad as og
 import scenegen
+from tests.gpu_helpers import check_gradients, splat_grads
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -19,22 +20,6 @@ def R():
         pytest.skip("no GPU")
     from paper_2503_07946_amd.render import get_renderer
     return get_renderer(0)
-
-
-def _compare(g_gpu, g_ora, rel_l2=1e-3, rel_entry=1e-2):
-    report = {}
-    for k in GROUPS:
-        a = g_gpu[k].astype(np.float64).reshape(g_ora[k].shape)
-        o = g_ora[k]
-        nrm = np.linalg.norm(o)
-        rl2 = np.linalg.norm(a - o) / max(nrm, 1e-30)
-        scale = np.maximum(np.abs(o), 1e-2 * np.abs(o).max())
-        worst = float((np.abs(a - o) / np.maximum(scale, 1e-30)).max())
-        report[k] = (rl2, worst)
-    for k, (rl2, worst) in report.items():
-        assert rl2 <= rel_l2, f"{k}: relative L2 {rl2:.2e}; {report}"
-        assert worst <= rel_entry, f"{k}: worst entry {worst:.2e}; {report}"
-    return report
 
 
 def _gpu_grad(R, scene, view, dL):
@@ -74,21 +59,25 @@ def test_gradients_match_oracle(R, case, report):
     scene, views, kind = _case(case)
     v = views[0]
     ora = oracle.render(scene, v)
-    mask = (ora.flags == 0).astype(np.float64)
+    # no gradient through pixels where the oracle took a decision within FP32
+    # reach of its threshold (the two sides may differ there by a contribution)
+    mask = (ora.fbound == 0).astype(np.float64)
     if kind == "l1":
         target = scenegen.target_image(2002, v.W, v.H).astype(np.float64)
         dL = og.l1_grad_image(ora.image, target)
     else:
         dL = np.random.default_rng(7).normal(size=(3, v.H, v.W))
-    dL = (dL * mask[None]).astype(np.float32)     # no gradient through flagged pixels
-    g_gpu, _ = _gpu_grad(R, scene, v, dL)
+    dL = (dL * mask[None]).astype(np.float32)
+    assert mask.mean() >= 0.99
+    g_gpu, b = _gpu_grad(R, scene, v, dL)
     g_ora, _ = og.grad(scene, v, dL.astype(np.float64))
     lam_gpu, lam_ora = g_gpu.pop("lambda").astype(np.float64), g_ora.pop("lambda")
     lam_err = np.abs(lam_gpu - lam_ora) / np.maximum(np.abs(lam_ora), 1e-6 * np.abs(g_ora["alpha"]).sum())
     report("lambda_grad_parity", case=case, rel=lam_err.tolist(), gpu=lam_gpu.tolist(), oracle=lam_ora.tolist())
     assert np.all(lam_err <= 1e-3), (lam_gpu, lam_ora)
-    rep = _compare(g_gpu, g_ora)
-    report("grad_parity", case=case, **{k: {"rel_l2": a, "worst_entry": b} for k, (a, b) in rep.items()})
+    d_ora = og.grad_splats(scene, v, dL.astype(np.float64))
+    rep = check_gradients(g_gpu, splat_grads(b, 0), g_ora, d_ora, og.splat_jacobian(scene, v))
+    report("grad_parity", case=case, masked_pixels=int((mask == 0).sum()), **rep)
 
 
 def test_autograd_function_matches_library_backward(R):

@@ -116,3 +116,83 @@ def test_x20_closed_form_gradients_single_gaussian():
         assert g["sh"][ch, 0] == pytest.approx(expect, rel=1e-12)
     expect_a = sum((w[ch] * np.where(live, e, 0.0)).sum() * (rgb[ch] - bg[ch]) for ch in range(3))
     assert g["alpha"][0] == pytest.approx(expect_a, rel=1e-12)
+
+
+def _scene64(sc):
+    """The scene with FP64 planes (so perturbations are not rounded)."""
+    return scenegen.Scene(*(np.asarray(getattr(sc, k), np.float64).copy()
+                            for k in ("mu_p", "mu_t", "mu_d", "L", "alpha", "sh")))
+
+
+def _splat_values(s, v):
+    o = oracle.slice_(s, v)
+    pr = oracle.project(o, s.sh, v)
+    return np.concatenate([pr.mean2d, pr.conic, o.alpha_c[None], pr.rgb], 0)
+
+
+def test_splat_jacobian_matches_central_differences_of_the_c_path():
+    """og.splat_jacobian (autograd of the PyTorch slice and projection)
+    against FP64 central differences of the independent C slice and
+    projection, for every parameter of a few Gaussians of a correlated scene."""
+    sc = scenegen.make_scene(40, 71, sigma_off=0.15)
+    v = scenegen.make_views(1, 71, r=3.0, W=32, H=32)[0]
+    J = og.splat_jacobian(sc, v)
+    base = _scene64(sc)
+    vis = oracle.project(oracle.slice_(sc, v), sc.sh, v).visible
+    checked = 0
+    for g in np.nonzero(vis)[0][:4]:
+        for k in og.PARAMS:
+            arr = getattr(base, k)
+            planes = 1 if arr.ndim == 1 else arr.shape[0]
+            for p in range(planes):
+                idx = (g,) if arr.ndim == 1 else (p, g)
+                h = 1e-6 * max(1.0, abs(arr[idx]))
+                sp, sm = _scene64(sc), _scene64(sc)
+                getattr(sp, k)[idx] += h
+                getattr(sm, k)[idx] -= h
+                fd = (_splat_values(sp, v)[:, g] - _splat_values(sm, v)[:, g]) / (2 * h)
+                np.testing.assert_allclose(J[k][:, p, g], fd, rtol=1e-5, atol=1e-6 * max(1.0, np.abs(fd).max()))
+                checked += 1
+    assert checked == 4 * 84
+
+
+def test_splat_gradients_match_central_differences_and_the_chain_rule():
+    """og.grad_splats against FP64 central differences of the C compositing
+    in each splat value, and chained through og.splat_jacobian it gives
+    og.grad's parameter gradients."""
+    sc, views = scenegen.config0()
+    v = views[0]
+    dL = np.random.default_rng(5).normal(size=(3, v.H, v.W))
+    d = og.grad_splats(sc, v, dL)
+    sl = oracle.slice_(sc, v)
+    pr = oracle.project(sl, sc.sh, v)
+
+    def loss(s2, p2):
+        return float((oracle.composite(s2, p2, v, banded=False).image * dL).sum())
+
+    rng = np.random.default_rng(6)
+    checked = 0
+    for g in rng.choice(np.nonzero(pr.visible)[0], 12, replace=False):
+        for j in range(len(og.SPLAT)):
+            scale = [1.0, 1.0, *([float(np.abs(pr.conic[:, g]).max())] * 3), float(sl.alpha_c[g]), 1.0, 1.0, 1.0][j]
+            h = 1e-5 * scale
+            vals = []
+            for sgn in (1, -1, 0.5, -0.5):
+                s2 = oracle.Sliced(sl.mu_c, sl.cov_c, sl.alpha_c.copy(), None, None, None)
+                p2 = oracle.Projected(pr.mean2d.copy(), pr.conic.copy(), pr.depth, pr.rgb.copy(), pr.rect,
+                                      pr.visible, pr.box)
+                tgt = [p2.mean2d[0], p2.mean2d[1], p2.conic[0], p2.conic[1], p2.conic[2], s2.alpha_c,
+                       p2.rgb[0], p2.rgb[1], p2.rgb[2]][j]
+                tgt[g] += sgn * h
+                vals.append(loss(s2, p2))
+            fd, fd2 = (vals[0] - vals[1]) / (2 * h), (vals[2] - vals[3]) / h
+            if abs(fd - fd2) > 1e-5 * max(1e-3, abs(fd)):
+                continue   # a discrete decision moved within the step
+            assert d[j, g] == pytest.approx(fd, rel=1e-4, abs=1e-8)
+            checked += 1
+    assert checked > 80
+    J = og.splat_jacobian(sc, v)
+    g_full, _ = og.grad(sc, v, dL)
+    for k in og.PARAMS:
+        chain = np.einsum("jpn,jn->pn", J[k], d).reshape(g_full[k].shape)
+        np.testing.assert_allclose(chain, g_full[k], rtol=0, atol=1e-12 * np.abs(g_full[k]).max())
