@@ -346,6 +346,25 @@ sd7_status sd7_rasterize(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t 
 sd7_status sd7_render(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t pair_capacity,
                       void* ws, size_t ws_bytes, sd7_stream stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, serving loops that must not call hipMalloc, harnesses that forbid
+ * it.  sd7_render over a workspace the library owns instead of one the caller
+ * passes: one static array of SD7_STATIC_WS_BYTES per device, held from the
+ * library's load until the process ends.  For scale, one 200,000-Gaussian
+ * 800x800 frame with a 1.5M-pair arena needs 53 MiB.  Frames whose sd7_plan()
+ * size exceeds it are refused with SD7_EWORKSPACE before anything is enqueued.
+ * The caller still owns the scene arrays and the frames' outputs; the call
+ * allocates nothing.  counts_out (device, nf x SD7_CNT_WORDS uint32 words, or
+ * NULL) receives the frames' counters and flags when the render ends, e.g.
+ * whether the pair arena overflowed.  Every call on one device shares that
+ * device's array and finds the previous call's intermediates in it (the
+ * render clears what it needs cleared): calls that overlap on one device, from
+ * any stream, thread or context, race, and the caller must serialize them.
+ * Outputs are bitwise those of sd7_render with the same frames and capacity. */
+#define SD7_STATIC_WS_BYTES 67108864u /* 64 MiB */
+sd7_status sd7_render_static(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t pair_capacity,
+                             uint32_t* counts_out, sd7_stream stream);
+
 /* Reverse of the compositing (Sec. 4.4, differentiable rasterization): each
  * pixel walks the list entries it consumed back to front from its final_T,
  * recomputing transmittance and the colour behind each entry (no per-pixel

@@ -18,6 +18,7 @@ SD7_CNT_KEPT, SD7_CNT_PAIRS, SD7_CNT_PAIR_BASE, SD7_CNT_FLAGS = 0, 1, 2, 3
 SD7_CNT_NEEDED = 4          # pairs the frame needs (also written on overflow)
 SD7_CNT_WORDS = 16
 SD7_AGR_WEIGHTS = 9443      # floats of one scene's AGR weights (sd7.h)
+SD7_STATIC_WS_BYTES = 64 << 20  # the library-owned workspace of sd7_render_static
 
 P = ctypes.c_void_p
 f32 = ctypes.c_float
@@ -72,7 +73,7 @@ STAGES = ("sd7_slice", "sd7_project", "sd7_slice_project", "sd7_bin", "sd7_raste
           "sd7_rasterize_backward", "sd7_project_backward", "sd7_slice_backward")
 EXPORTS = ("sd7_create", "sd7_destroy", "sd7_last_error", "sd7_plan", "sd7_read_counts",
            "sd7_cov_decompose", "sd7_split_test", "sd7_adam_step", "sd7_prune_workspace_size",
-           "sd7_prune_count", "sd7_prune_apply") + STAGES
+           "sd7_prune_count", "sd7_prune_apply", "sd7_render_static") + STAGES
 
 
 class Sd7Error(RuntimeError):
@@ -113,6 +114,8 @@ def load(path: str = LIB_PATH):
         fn.argtypes = [P, ctypes.POINTER(Sd7Frame), ctypes.c_int, ctypes.c_int64, P,
                        ctypes.c_size_t, P]
         fn.restype = ctypes.c_int32
+    L.sd7_render_static.argtypes = [P, ctypes.POINTER(Sd7Frame), ctypes.c_int, ctypes.c_int64, P, P]
+    L.sd7_render_static.restype = ctypes.c_int32
     L.sd7_read_counts.argtypes = [P, ctypes.c_int, P, ctypes.POINTER(ctypes.c_uint32), P]
     L.sd7_read_counts.restype = ctypes.c_int32
     L.sd7_cov_decompose.argtypes = [P, ctypes.c_int64, P, P, P, P]

@@ -50,6 +50,13 @@ sd7_status fail(sd7_status code, const char* fmt, ...)
 
 constexpr size_t kAlign = 256;
 constexpr int kRing = 64;             // pinned staging slots for frame tables
+
+// The workspace of sd7_render_static: one per device, held from the library's
+// load until the process ends.  Host code never passes this name to a kernel
+// or a copy (on the host it is only a stand-in for the symbol): sd7_create
+// looks up its device address with hipGetSymbolAddress and keeps it in the
+// context.
+static __device__ __align__(256) unsigned char scratch[SD7_STATIC_WS_BYTES];
 constexpr int kPersistentBlocks = 2048;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -264,6 +271,7 @@ sd7_status make_plan(const sd7_frame* fr, int nf, int64_t cap, Plan& P, bool nee
 
 struct sd7_ctx {
     int device = 0;
+    char* scratch = nullptr;     // device address of this device's `scratch` array
     char* ring = nullptr;        // pinned host staging for frame tables
     size_t slot_bytes = 0;
     hipEvent_t ev[kRing];
@@ -638,9 +646,13 @@ sd7_status sd7_create(int device, sd7_ctx** out)
     HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tile_count),
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)(sizeof(uint32_t) * kMaxCountTiles)));
+    void* sp = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)));
+    if (!sp) return fail(SD7_EHIP, "hipGetSymbolAddress gave no address for the static workspace");
     sd7_ctx* c = new (std::nothrow) sd7_ctx();
     if (!c) return fail(SD7_ENOMEM, "out of host memory");
     c->device = device;
+    c->scratch = static_cast<char*>(sp);
     c->slot_bytes = align_up(sizeof(FrameDev) * SD7_MAX_FRAMES);
     hipError_t e = hipHostMalloc((void**)&c->ring, c->slot_bytes * kRing, hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -704,6 +716,29 @@ STAGE(sd7_render, false, {
     return do_raster(c);
 })
 STAGE(sd7_rasterize_backward, true, { return do_raster_bwd(c); })
+
+sd7_status sd7_render_static(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t cap, uint32_t* counts_out,
+                             sd7_stream stream)
+{
+    g_err[0] = 0;
+    if (!ctx) return fail(SD7_EINVAL, "ctx is NULL");
+    Call c;
+    sd7_status s = make_plan(frames, nf, cap, c.P, false);
+    if (s != SD7_OK) return s;
+    if (c.P.L.bytes > (size_t)SD7_STATIC_WS_BYTES)
+        return fail(SD7_EWORKSPACE, "these frames need a %zu-byte workspace; the static one holds %zu",
+                    c.P.L.bytes, (size_t)SD7_STATIC_WS_BYTES);
+    s = begin(ctx, frames, nf, cap, ctx->scratch, SD7_STATIC_WS_BYTES, stream, c, false);
+    if (s != SD7_OK) return s;
+    if ((s = do_slice_project(c)) != SD7_OK) return s;
+    if ((s = do_bin(c)) != SD7_OK) return s;
+    if ((s = do_raster(c)) != SD7_OK) return s;
+    if (counts_out) {
+        k_copy_u32<<<1, 256, 0, c.st>>>(counts_out, c.counts, (uint32_t)(SD7_CNT_WORDS * nf));
+        LAUNCH_CHECK("k_copy_u32");
+    }
+    return SD7_OK;
+}
 STAGE(sd7_project_backward, true, { return do_project_bwd(c); })
 STAGE(sd7_slice_backward, true, { return do_slice_bwd(c, frames, nf); })
 

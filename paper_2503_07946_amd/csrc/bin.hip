@@ -330,6 +330,11 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, size_t count, uint32_t valu
         p[i] = value;
 }
 
+__global__ void k_copy_u32(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src, uint32_t count)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
 // Segments of the depth sort.  segs_all: every Gaussian (the compacting first
 // pass); segs_kept: the kept ones.  One wave, lane f = frame f (at most 64
 // frames); offsets are wave prefix sums.

@@ -267,6 +267,17 @@ class Renderer:
         self.stage("sd7_rasterize", b, stream)
         return b
 
+    def render_static(self, frames, capacity: int, counts_out: torch.Tensor | None = None, stream=None):
+        """sd7_render over the library's own per-device workspace (no workspace
+        argument; nothing is allocated).  counts_out: optional int32 device
+        tensor of len(frames) x SD7_CNT_WORDS words for the frames' counters."""
+        st = torch.cuda.current_stream(self.device) if stream is None else stream
+        cs = self.cstruct(frames)
+        if counts_out is not None:
+            assert counts_out.is_cuda and counts_out.numel() >= len(frames) * L.SD7_CNT_WORDS
+        L.check(self.lib.sd7_render_static(self.ctx, cs, len(frames), int(capacity), _ptr(counts_out),
+                                           ctypes.c_void_p(st.cuda_stream)))
+
     def render(self, scene: GaussianScene, view, capacity=None, stream=None, count=False) -> Batch:
         return self.render_frames(self.make_frames([(scene, view)], count=count), capacity, stream)
 
