@@ -26,10 +26,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# FP32 peak without packed math: 256 CUs x 64 lanes x one FMA (2 operations)
-# per lane per clock x 2.4 GHz.  (The published 157.3 TFLOP/s counts packed
-# FP32 FMAs, which this library is built without.)
-FP32_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# MI355X's published FP32 vector peak (it counts packed FP32 FMAs: two per lane
+# per clock), and the peak without packed math, which this library is built
+# without: 256 CUs x 64 lanes x one FMA (2 operations) per clock x 2.4 GHz.
+FP32_PEAK_TFLOPS = 157.3
+FP32_NONPACKED_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 
 # Rasterizer roofline, in algorithmic FP32 operations of the compositing as the
 # method defines it.  Per (pixel, splat) test -- every list entry a pixel
@@ -88,13 +89,19 @@ def parse():
     ap.add_argument("--gaussians", type=int, default=200_000)
     ap.add_argument("--plain-frames", type=int, default=20, help="frames timed one per call")
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--cpu-crop", type=int, default=448)
+    ap.add_argument("--cpu-crop", type=int, default=128, help="side of the centre crop timed with all threads")
+    ap.add_argument("--small", type=int, default=1,
+                    help="also time the small workload (1,000 Gaussians, one 64x64 frame per call)")
+    ap.add_argument("--stress", type=int, default=1,
+                    help="also time the stress workload (4M Gaussians, 64 views of 1920x1080, forward + backward)")
+    ap.add_argument("--stress-inflight", type=int, default=8)
     ap.add_argument("--serve", type=int, default=1, help="also run the serving comparison")
     ap.add_argument("--agr", type=int, default=1,
                     help="also time the full variant with adaptive Gaussian refinement (seeded weights)")
-    ap.add_argument("--serve-requests", type=int, default=240)
-    ap.add_argument("--serve-warmup", type=int, default=40)
-    ap.add_argument("--serve-qps", type=float, default=0.0, help="0: 0.9x the plain path's capacity")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per offered load")
+    ap.add_argument("--serve-warmup", type=int, default=100)
+    ap.add_argument("--serve-loads", type=str, default="0.5,0.9,1.25,2,4",
+                    help="offered loads as multiples of the plain path's capacity")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--serve-sizes", type=str, default="100000,300000,1000000,2000000")
     ap.add_argument("--train", type=int, default=1,
@@ -119,8 +126,12 @@ def copy_probe(mib: int):
 
 
 def serve_bench(a, R, L):
-    """Serving: resident scenes, a Poisson stream of (scene, camera, t) requests
-    at mixed resolutions; continuous batching vs one frame per call."""
+    """Serving: four resident scenes, Poisson streams of (scene, camera, t)
+    requests at mixed resolutions offered at several loads around the plain
+    path's capacity; continuous batching vs one request per call.  Per load:
+    `serve_warmup` + `serve_requests` requests (the first `serve_warmup` not
+    counted), p50/p99 latency (arrival to completion) and the throughput each
+    path sustains; the highest is each path's ceiling."""
     import numpy as np
     import torch
 
@@ -132,30 +143,39 @@ def serve_bench(a, R, L):
     scenes = [GaussianScene.from_host(s) for s in scenegen.config3_scenes(sizes)]
     torch.cuda.synchronize()
     ex = serve.GpuExecutor(R, scenes, nstreams=2)
-    # learn pair counts and the plain path's service time on a calibration stream
-    cal = serve.default_requests(48, 1000.0, sizes, seed=301)
+    # learn the pair counts (scene, resolution) and the plain path's service
+    # time on a calibration stream
+    cal = serve.default_requests(64, 1000.0, sizes, seed=301)
     for r in cal:
-        ex.est[(r.scene, r.view.W, r.view.H)] = max(
-            ex.est.get((r.scene, r.view.W, r.view.H), 0),
-            int(R.read_counts(R.render_frames(R.make_frames([(scenes[r.scene], r.view)]),
-                                              capacity=ex.pair_estimate(r)))[0, L.SD7_CNT_PAIRS]))
+        ex.render_one(r)
+    for r in cal:
+        ex.render_one(r)
     t0 = time.perf_counter()
     for r in cal:
         ex.render_one(r)
     plain_service = (time.perf_counter() - t0) / len(cal)
-    qps = a.serve_qps if a.serve_qps > 0 else 0.9 / plain_service
+    cap_plain = 1.0 / plain_service
     n = a.serve_requests + a.serve_warmup
-    reqs_p = serve.default_requests(n, qps, sizes, seed=300)
-    reqs_b = serve.default_requests(n, qps, sizes, seed=300)
-    print(f"[bench] serving: {n} requests at {qps:.1f} QPS (plain service {1e3 * plain_service:.2f} ms)",
-          file=sys.stderr, flush=True)
-    st_p = serve.run_plain(ex, reqs_p)
-    sch = serve.Scheduler(ex, serve.budget_from_gb(a.serve_budget_gb), max_slots=16, max_inflight=2)
-    st_b = sch.run(reqs_b)
-    sp, sb = st_p.summary(skip=a.serve_warmup), st_b.summary(skip=a.serve_warmup)
-    return {"qps": round(qps, 2), "requests": a.serve_requests, "scenes": sizes,
-            "resolutions": [list(r) for r in scenegen.SERVE_RES], "hbm_budget_gb": a.serve_budget_gb,
-            "plain": sp, "batched": sb}
+    points = []
+    for load in [float(x) for x in a.serve_loads.split(",")]:
+        qps = load * cap_plain
+        print(f"[bench] serving: {n} requests at {qps:.0f} QPS ({load}x the plain capacity)",
+              file=sys.stderr, flush=True)
+        st_p = serve.run_plain(ex, serve.default_requests(n, qps, sizes, seed=300))
+        sch = serve.Scheduler(ex, serve.budget_from_gb(a.serve_budget_gb), max_slots=16, max_inflight=2)
+        st_b = sch.run(serve.default_requests(n, qps, sizes, seed=300))
+        points.append({"load": load, "offered_qps": round(qps, 1),
+                       "plain": st_p.summary(skip=a.serve_warmup), "batched": st_b.summary(skip=a.serve_warmup)})
+    ceil_p = max(p["plain"]["throughput_fps"] or 0 for p in points)
+    ceil_b = max(p["batched"]["throughput_fps"] or 0 for p in points)
+    return {"scenes": sizes, "resolutions": [list(r) for r in scenegen.SERVE_RES],
+            "hbm_budget_gb": a.serve_budget_gb, "requests_per_load": a.serve_requests,
+            "warmup_per_load": a.serve_warmup, "plain_service_ms": round(1e3 * plain_service, 3),
+            "plain_path": "one request per call: one sd7_render with the pair count learned for its "
+                          "(scene, resolution), then one wait for it (a re-render if the arena overflowed)",
+            "throughput_ceiling_fps": {"plain": round(ceil_p, 1), "batched": round(ceil_b, 1),
+                                       "batched_over_plain": round(ceil_b / ceil_p, 3) if ceil_p else None},
+            "loads": points}
 
 
 def run_steps(R, batches, steps, streams, record_stage=None):
@@ -214,17 +234,20 @@ def copy_bandwidth(mib: int = 1024, reps: int = 10):
 def stage_hbm_fracs(stage_ms, n, views, batch, kept, pairs, tiles, copy_gb_s=None):
     """Algorithmic HBM bytes of a step's slice + project and binning stages and
     the fraction of the 8 TB/s peak their serial times reach (and of the
-    measured copy bandwidth when given).  Slice + project:
-    the 336 B of scene parameters read once per launch (a batch of frames
-    sharing the scene), and per (Gaussian, frame) the 108 B written (sliced mean,
-    covariance and opacity 40 B, splat record 48 B, footprint 16 B, depth key
-    4 B).  Binning: the depth sort's 64 B per kept Gaussian (four passes, each
-    reading and writing a key and a value), 4 B per pair of the tile lists and
-    8 B per tile range."""
+    measured copy bandwidth when given).  Slice + project: the 336 B of scene
+    parameters read once per launch (the frames of a launch share the scene;
+    144 B of the slice's inputs, 192 B of SH coefficients), and per frame the
+    68 B a kept Gaussian's splat needs (48 B record, 16 B tile footprint, 4 B
+    depth key) and the 4 B key that marks a culled one.  Binning: the depth
+    keys read (4 B per Gaussian), the depth sort's 64 B per kept Gaussian (four
+    passes, each reading and writing a key and a value), the footprints read
+    in depth order (16 B per kept Gaussian), 4 B per pair of the tile lists
+    and 8 B per tile range."""
     launches = -(-views // batch)
     out = {}
-    for name, b in (("sd7_slice_project", 336 * n * launches + 108 * n * views),
-                    ("sd7_bin", 64 * kept + 4 * pairs + 8 * tiles)):
+    sp = 336 * n * launches + 68 * kept + 4 * (n * views - kept)
+    bn = 4 * n * views + 64 * kept + 16 * kept + 4 * pairs + 8 * tiles
+    for name, b in (("sd7_slice_project", sp), ("sd7_bin", bn)):
         t = stage_ms[name] * 1e-3
         out[name] = {"algorithmic_bytes": int(b), "gb_s": round(b / t / 1e9, 1),
                      "frac": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}
@@ -357,6 +380,199 @@ def agr_bench(a, R, L, scene, views, streams):
             "overflowed_frames": over, "weights": "scenegen.agr_weights(1)"}
 
 
+def stress_bench(a, R, L, scene, views, target):
+    """The stress workload: 4,000,000 Gaussians with ill-conditioned (t, d)
+    blocks, 64 views of 1920x1080, `stress_inflight` views resident at once
+    (one set of launches), each followed by the full reverse pass of an L1
+    loss against the seeded target.  One untimed pass sizes each group's pair
+    arena; the timed pass brackets every stage of every group with HIP events
+    on one stream."""
+    import numpy as np
+    import torch
+
+    from paper_2503_07946_amd.render import GaussianScene, PARAMS
+
+    gs = GaussianScene.from_host(scene)
+    tgt = torch.as_tensor(target, device="cuda")
+    V = a.stress_inflight
+    groups = [views[i:i + V] for i in range(0, len(views), V)]
+    grads = [{k: torch.empty_like(getattr(gs, k)) for k in PARAMS} for _ in range(V)]
+    for g in grads:
+        g["lambda"] = torch.zeros(2, dtype=torch.float32, device="cuda")
+    outs = [(torch.empty((3, views[0].H, views[0].W), device="cuda"),
+             torch.empty((views[0].H, views[0].W), device="cuda"),
+             torch.empty((views[0].H, views[0].W), dtype=torch.int32, device="cuda")) for _ in range(V)]
+    caps = []
+    for gv in groups:   # untimed: exact pair counts per group
+        fr = R.make_frames([(gs, v) for v in gv], outputs=outs[:len(gv)])
+        c = R.read_counts(R.render_frames(fr, exact=True))
+        caps.append(int(sum(-(-int(p) // L.SD7_PAIR_ROUND) * L.SD7_PAIR_ROUND for p in c[:, L.SD7_CNT_NEEDED])))
+        torch.cuda.empty_cache()
+    cap = int(max(caps) * 1.02) + L.SD7_PAIR_ROUND * V
+    ws = None
+    names = ("sd7_slice_project", "sd7_bin", "sd7_rasterize", "loss_gradient",
+             "sd7_rasterize_backward", "sd7_project_backward", "sd7_slice_backward")
+    st = torch.cuda.current_stream()
+    per = {n: 0.0 for n in names}
+    pairs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for gv in groups:
+        fr = R.make_frames([(gs, v) for v in gv], outputs=outs[:len(gv)])
+        for k, f in enumerate(fr):
+            f.grads = grads[k]
+            f.dL_dimage = torch.empty_like(f.image)
+        b = R.batch(fr, cap, ws)
+        ws = b.ws
+        b.cstruct = R.cstruct(fr)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+        ev[0].record(st)
+        for k, name in enumerate(names):
+            if name == "loss_gradient":
+                for f in fr:
+                    torch.sign(f.image - tgt, out=f.dL_dimage)
+                    f.dL_dimage.mul_(1.0 / tgt.numel())
+                    f.grads["lambda"].zero_()
+            else:
+                R.stage(name, b, stream=st)
+            ev[k + 1].record(st)
+        torch.cuda.synchronize()
+        for k, name in enumerate(names):
+            per[name] += ev[k].elapsed_time(ev[k + 1])
+        c = R.read_counts(b)
+        assert not np.any(c[:, L.SD7_CNT_FLAGS] & L.SD7_FLAG_PAIR_OVERFLOW)
+        pairs += c[:, L.SD7_CNT_PAIRS].tolist()
+    dt = time.perf_counter() - t0
+    nv = len(views)
+    stage = {n: round(per[n] / nv, 4) for n in names}
+    return {"workload": f"{scene.n // 1000000}M 7D Gaussians (condition number of the (t, d) block up to 1e4), "
+                        f"{nv} views {views[0].W}x{views[0].H}, {V} in flight, forward + reverse pass per view",
+            "ms_per_view": round(1e3 * dt / nv, 3), "views": nv, "inflight": V,
+            "stage_ms_per_view": stage, "largest_stage": max(stage, key=stage.get),
+            "pairs_per_view_mean": int(np.mean(pairs))}
+
+
+def small_bench(R, L, reps: int = 300):
+    """The small workload (1,000 Gaussians, one 64x64 view): launch-bound, so
+    reported as microseconds per frame: one sd7_render call waited for each
+    time (latency), and back-to-back calls (throughput)."""
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_2503_07946_amd.render import GaussianScene
+
+    scene, views = scenegen.config0()
+    gs = GaussianScene.from_host(scene)
+    c = R.read_counts(R.render(gs, views[0]))
+    b = R.batch(R.make_frames([(gs, views[0])]), int(c[0, L.SD7_CNT_NEEDED]) + L.SD7_PAIR_ROUND)
+    for _ in range(20):
+        R.stage("sd7_render", b)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        R.stage("sd7_render", b)
+        torch.cuda.synchronize()
+        lat.append(1e6 * (time.perf_counter() - t0))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        R.stage("sd7_render", b)
+    torch.cuda.synchronize()
+    return {"workload": "1,000 7D Gaussians, one 64x64 view per call",
+            "latency_us_p50": round(float(np.percentile(lat, 50)), 1),
+            "latency_us_p99": round(float(np.percentile(lat, 99)), 1),
+            "back_to_back_us_per_frame": round(1e6 * (time.perf_counter() - t0) / reps, 1)}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_bench(a, scene1, views1, stress=None):
+    """The FP64 CPU oracle (brute force: every visible Gaussian tested at each
+    pixel until it stops) on bounded samples of the workloads, with all host
+    threads and with one: the throughput workload's centre crops (FPS
+    extrapolated to the 800x800 frame, labelled so), the small workload's full
+    frame, and 64x64 centre crops of the training and stress workloads,
+    forward (C oracle) and reverse (PyTorch FP64 autograd, on the Gaussians
+    whose opacity box reaches the crop; the others add nothing there)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import oracle.grad as og
+    import scenegen
+
+    nall = oracle.num_threads()
+    W, H = views1[0].W, views1[0].H
+
+    def crop_render(scene, view, crop, nt):
+        oracle.set_threads(nt)
+        t0 = time.perf_counter()
+        o = oracle.render(scene, view, crop=crop, banded=False)
+        dt = time.perf_counter() - t0
+        tests = int(o.ntest.sum())
+        return o, dt, tests
+
+    out = {"cpu_model": cpu_model(), "threads": nall}
+    c1 = {}
+    for nt, cs in ((nall, a.cpu_crop), (1, 64)):
+        crop = ((W - cs) // 2, (H - cs) // 2, cs, cs)
+        _, dt, tests = crop_render(scene1, views1[0], crop, nt)
+        c1[nt] = {"threads": nt, "crop": [cs, cs], "seconds": round(dt, 3), "pair_tests": tests,
+                  "pair_tests_per_s": round(tests / dt, 1),
+                  "fps_extrapolated": round(cs * cs / (W * H) / dt, 6)}
+    out["throughput_workload"] = c1
+    sc0, v0 = scenegen.config0()
+    c0 = {}
+    for nt in (1, nall):
+        crop_render(sc0, v0[0], None, nt)
+        _, dt, tests = crop_render(sc0, v0[0], None, nt)
+        c0[nt] = {"threads": nt, "ms_per_frame": round(1e3 * dt, 3), "pair_tests_per_s": round(tests / dt, 1)}
+    out["small_workload_full_frame"] = c0
+
+    def crop_fwd_bwd(scene, view, target, nt):
+        oracle.set_threads(nt)
+        torch.set_num_threads(nt)
+        crop = ((view.W - 64) // 2, (view.H - 64) // 2, 64, 64)
+        t0 = time.perf_counter()
+        sl = oracle.slice_(scene, view)
+        pr = oracle.project(sl, scene.sh, view)
+        x0, y0 = crop[0], crop[1]
+        near = np.nonzero(pr.visible & (pr.box[2] >= x0 - 1) & (pr.box[0] <= x0 + 65) &
+                          (pr.box[3] >= y0 - 1) & (pr.box[1] <= y0 + 65))[0]
+        sub = scene.subset(near)
+        o = oracle.render(sub, view, crop=crop, banded=False)
+        t1 = time.perf_counter()
+        dL = og.l1_grad_image(o.image, target[:, y0:y0 + 64, x0:x0 + 64].astype(np.float64))
+        og.grad(sub, view, dL, crop=crop)
+        t2 = time.perf_counter()
+        return {"threads": nt, "crop": [64, 64], "gaussians_reaching_crop": int(len(near)),
+                "forward_s": round(t1 - t0, 3), "reverse_s": round(t2 - t1, 3),
+                "pair_tests_per_s": round(int(o.ntest.sum()) / (t1 - t0), 1)}
+
+    sc2, v2, t2 = scenegen.config2()
+    out["training_workload_crop"] = crop_fwd_bwd(sc2, v2[0], t2, nall)
+    if stress is not None:
+        s4, v4, t4 = stress
+        out["stress_workload_crop"] = crop_fwd_bwd(s4, v4[0], t4, nall)
+    oracle.set_threads(nall)
+    torch.set_num_threads(nall)
+    return {"value": c1[nall]["fps_extrapolated"], "unit": "FPS", "cores": nall, "kind": "oracle",
+            "sample": f"throughput workload: {a.cpu_crop}x{a.cpu_crop} centre crop of view 0 with all {nall} "
+                      f"threads (all 200k Gaussians sliced and projected, brute-force compositing), "
+                      f"{c1[nall]['seconds']} s; FPS extrapolated to the full 800x800 frame",
+            "one_thread": c1[1], **out}
+
+
 def pct(xs, q):
     import numpy as np
     return float(np.percentile(np.asarray(xs, dtype=float), q)) if len(xs) else None
@@ -440,7 +656,9 @@ def main():
     flops_l = RASTER_OPS_PER_TEST * tests_l + RASTER_OPS_PER_CONTRIBUTION * contribs_l
     achieved = flops_l / t_r / 1e12
     roofline = {"bound": "alu", "kernel": "k_raster", "achieved": round(achieved, 3),
-                "peak": round(FP32_PEAK_TFLOPS, 2), "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                "peak_without_packed_fp32": round(FP32_NONPACKED_PEAK_TFLOPS, 2),
+                "frac_without_packed_fp32": round(achieved / FP32_NONPACKED_PEAK_TFLOPS, 4),
                 "traffic": RASTER_TRAFFIC_BYTES if current else None,
                 "algorithmic_units": {"pixel_tests_per_launch": int(tests_l),
                                       "contributions_per_launch": int(contribs_l),
@@ -461,29 +679,25 @@ def main():
             R.stage("sd7_render", b)
             torch.cuda.synchronize()
             lat_batched += [1e3 * (time.perf_counter() - s0)] * b.nf
+    # plain: one frame per sd7_render call with the pair count learned for this
+    # scene and resolution (no read-back inside the frame), waited for
     lat_plain = []
+    cap1 = int(max(pairs) * 1.05) + L.SD7_PAIR_ROUND
     for v in views[:a.plain_frames]:
         s0 = time.perf_counter()
-        bp = R.render_frames(R.make_frames([(gs, v)]), capacity=batches[0].capacity, exact=True)
+        bp = R.batch(R.make_frames([(gs, v)]), cap1)
+        R.stage("sd7_render", bp)
         torch.cuda.synchronize()
         lat_plain.append(1e3 * (time.perf_counter() - s0))
     plain_fps = len(lat_plain) / (sum(lat_plain) / 1e3) if lat_plain else None
 
-    # -- FP64 CPU oracle on a bounded sample (a centre crop of view 0)
-    cpu = None
-    if a.cpu_baseline:
-        import oracle
-        cs = a.cpu_crop
-        crop = ((W - cs) // 2, (H - cs) // 2, cs, cs)
-        ts = time.perf_counter()
-        oracle.render(scene, views[0], crop=crop)
-        tc = time.perf_counter() - ts
-        full = tc * (W * H) / (cs * cs)
-        cpu = {"value": round(1.0 / full, 6), "unit": "FPS", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": f"{cs}x{cs} centre crop of view 0 (all 200k Gaussians sliced and projected, "
-                         f"brute-force compositing), {tc:.2f} s; FPS extrapolated to the full 800x800 frame"}
-
+    small = small_bench(R, L) if a.small else None
+    stress_in = scenegen.config4() if (a.stress or a.cpu_baseline) else None
+    stress = stress_bench(a, R, L, *stress_in) if a.stress else None
+    torch.cuda.empty_cache()
+    # -- FP64 CPU oracle on bounded samples
+    cpu = cpu_baseline_bench(a, scene, views, stress_in) if a.cpu_baseline else None
+    del stress_in
     serving = serve_bench(a, R, L) if a.serve else None
     agr = agr_bench(a, R, L, scene, views, streams) if a.agr else None
     training = train_bench(a, R, L) if a.train else None
@@ -510,6 +724,8 @@ def main():
         "serving": serving,
         "agr": agr,
         "training": training,
+        "small": small,
+        "stress": stress,
     }
     print(json.dumps(out))
     return 0

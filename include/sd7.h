@@ -175,7 +175,15 @@ typedef struct {
     sd7_scene_grad grad;     /* out: backward only (may be NULL otherwise) */
     uint32_t* ncontrib;      /* optional out [H][W]: splats that contributed to the pixel;
                                 NULL: not counted (the count costs one add per test) */
+    uint32_t outputs;        /* SD7_OUT_* bits: intermediates to keep in the workspace */
 } sd7_frame;
+
+/* sd7_frame.outputs: sd7_slice_project and sd7_render write a frame's sliced
+ * statistics (off_mu_c, off_cov_c, off_alpha_c) only when the frame asks for
+ * them with SD7_OUT_SLICED or has gradient buffers (grad.L non-NULL: a
+ * reverse pass will read them); sd7_slice always writes them.  A render
+ * without them writes 40 bytes less per (Gaussian, frame). */
+#define SD7_OUT_SLICED 1u
 
 /* Workspace layout.  Every offset is in bytes from the workspace base and a
  * multiple of 256.  Per-Gaussian arrays hold the frames back to back: frame f
@@ -185,13 +193,13 @@ typedef struct {
  *   off_mu_c     float  [3 planes]             conditional mean
  *   off_cov_c    float  [6 planes]             conditional covariance (xx,xy,xz,yy,yz,zz)
  *   off_alpha_c  float  [1 plane]              conditional opacity
- *   off_splat    float  [Ntot][12]             per Gaussian (AoS): u, v, A, B, C, lo,
+ *   off_splat    float  [Ntot][12]             per kept Gaussian (AoS; culled: not written): u, v, A, B, C, lo,
  *                                              r, g, b, 16 C, alpha_c, depth where
  *                                              (A, B, C) = -log2(e) (a/2, b, c/2) for the
  *                                              conic q = a dx^2 + 2b dx dy + c dy^2 and
  *                                              lo = log2(alpha_c), so that
  *                                              alpha_c e^{-q/2} = 2^(A dx^2 + B dx dy + C dy^2 + lo)
- *   off_rect     uint32 [Ntot][4]              tile footprint: the tile box (x0 | y0 << 16,
+ *   off_rect     uint32 [Ntot][4]              kept Gaussians' tile footprint: the tile box (x0 | y0 << 16,
  *                                              x1 | y1 << 16; x1, y1 exclusive), then row
  *                                              trims: word 2 for box rows 0..3, word 3 for
  *                                              rows m..m+3 (m = h - 4 if the box has h > 8
@@ -321,7 +329,8 @@ sd7_status sd7_plan(const sd7_frame* frames, int nf, int64_t pair_capacity, sd7_
 /* Sec. 4.2: writes mu_c, cov_c, alpha_c; zeroes the counters. */
 sd7_status sd7_slice(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t pair_capacity,
                      void* ws, size_t ws_bytes, sd7_stream stream);
-/* Sec. 4.4 projection: writes splat, rect, depth_key and the KEPT counters. */
+/* Sec. 4.4 projection: writes depth_key, the KEPT counters and, for kept
+ * Gaussians, splat and rect. */
 sd7_status sd7_project(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t pair_capacity,
                        void* ws, size_t ws_bytes, sd7_stream stream);
 /* sd7_slice followed by sd7_project in one pass (Sec. 4.2, Sec. 4.4): frames

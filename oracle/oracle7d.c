@@ -460,7 +460,7 @@ int ora_composite(int64_t n, const double* mean2d, const double* conic, const do
                   const double* depth, const double* rgb, const double* errpar, int64_t m,
                   const int64_t* order, const ora_view* v, int x0, int y0, int w, int h,
                   const ora_flagcfg* fc, double* image, double* final_T, int32_t* ncontrib,
-                  uint64_t* chash, uint32_t* flags, double* fbound)
+                  uint64_t* chash, uint32_t* flags, double* fbound, int64_t* ntest)
 {
     const double bg[3] = {v->bg[0], v->bg[1], v->bg[2]};
     const int64_t npx = (int64_t)w * h;
@@ -489,7 +489,8 @@ int ora_composite(int64_t n, const double* mean2d, const double* conic, const do
             double eT = 0.0;     /* band of ln T accumulated so far */
             int have_prev = 0;
             double prev_z = 0, prev_ez = 0, prev_a = 0, prev_rgb[3] = {0, 0, 0}, prev_T = 0;
-            for (int64_t j = 0; j < m; ++j) {
+            int64_t j = 0;
+            for (; j < m; ++j) {
                 const int64_t g = order[j];
                 const double dx = mean2d[g] - pxc, dy = mean2d[n + g] - pyc;
                 const double ca = conic[g], cb = conic[n + g], cc = conic[2 * n + g];
@@ -586,6 +587,7 @@ int ora_composite(int64_t n, const double* mean2d, const double* conic, const do
             if (chash) chash[p] = hsh;
             if (flags) flags[p] = banded ? fl_imp : 0u;
             if (fbound) fbound[p] = banded ? 1.01 * fb : 0.0;
+            if (ntest) ntest[p] = j < m ? j + 1 : m;   /* Gaussians tested, the stopping one included */
         }
     }
     return 0;
@@ -646,7 +648,7 @@ int ora_render(int64_t n, const double* mu_p, const double* mu_t, const double* 
                const double* L, const double* alpha, const double* sh, const ora_view* v,
                int x0, int y0, int w, int h, const ora_flagcfg* fc,
                double* image, double* final_T, int32_t* ncontrib, uint64_t* chash,
-               uint32_t* flags, double* fbound)
+               uint32_t* flags, double* fbound, int64_t* ntest)
 {
     double* mu_c = (double*)malloc(sizeof(double) * 3 * n + 8);
     double* cov_c = (double*)malloc(sizeof(double) * 6 * n + 8);
@@ -669,7 +671,7 @@ int ora_render(int64_t n, const double* mu_p, const double* mu_t, const double* 
         int64_t m = ora_order(n, depth, vis, order);
         if (errpar) ora_fp32_model(n, mu_c, cov_c, v, errpar);
         ora_composite(n, mean2d, conic, alpha_c, depth, rgb, errpar, m, order, v, x0, y0, w, h, fc,
-                      image, final_T, ncontrib, chash, flags, fbound);
+                      image, final_T, ncontrib, chash, flags, fbound, ntest);
     }
     free(mu_c); free(cov_c); free(alpha_c); free(mean2d); free(conic);
     free(depth); free(rgb); free(rect); free(vis); free(order); free(errpar);

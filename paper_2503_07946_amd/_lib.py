@@ -14,6 +14,7 @@ SD7_MAX_FRAMES = 64
 SD7_TILE = 16
 SD7_PAIR_ROUND = 2048       # a frame's arena share is a multiple of this (sd7.h)
 SD7_FLAG_NONPOS_DIAG, SD7_FLAG_NONFINITE, SD7_FLAG_PAIR_OVERFLOW = 1, 2, 4
+SD7_OUT_SLICED = 1          # sd7_frame.outputs: keep the sliced statistics
 SD7_CNT_KEPT, SD7_CNT_PAIRS, SD7_CNT_PAIR_BASE, SD7_CNT_FLAGS = 0, 1, 2, 3
 SD7_CNT_NEEDED = 4          # pairs the frame needs (also written on overflow)
 SD7_CNT_WORDS = 16
@@ -52,7 +53,8 @@ class Sd7Adam(ctypes.Structure):
 
 class Sd7Frame(ctypes.Structure):
     _fields_ = [("scene", Sd7Scene), ("view", Sd7View), ("image", P), ("final_T", P),
-                ("last", P), ("dL_dimage", P), ("grad", Sd7SceneGrad), ("ncontrib", P)]
+                ("last", P), ("dL_dimage", P), ("grad", Sd7SceneGrad), ("ncontrib", P),
+                ("outputs", ctypes.c_uint32)]
 
 
 _OFFS = ["off_table", "off_counts", "off_mu_c", "off_cov_c", "off_alpha_c", "off_splat",

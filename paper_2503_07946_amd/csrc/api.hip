@@ -312,6 +312,7 @@ sd7_status upload_table(sd7_ctx* ctx, const sd7_frame* fr, int nf, const Plan& P
         D.t0 = (uint32_t)P.L.tile0[f];
         D.nch = P.nch[f];
         D.m0 = P.m0[f];
+        D.keep_sliced = (F.outputs & SD7_OUT_SLICED) || F.grad.L ? 1u : 0u;
         std::memcpy(D.R, F.view.R_wc, sizeof(D.R));
         std::memcpy(D.c, F.view.c, sizeof(D.c));
         D.fx = F.view.fx; D.fy = F.view.fy; D.cx = F.view.cx; D.cy = F.view.cy;

@@ -58,6 +58,7 @@ struct FrameDev {
     uint32_t nch;      // binning chunks (the kept Gaussians are cut into this many)
     uint32_t d_mode;   // 1: Gaussian i is conditioned on unit(mu_p,i - c)
     uint32_t m0;       // first entry of the frame's [chunk][tile] count matrix
+    uint32_t keep_sliced;  // 1: the fused slice/projection writes the sliced statistics
     float R[9];
     float c[3];
     float fx, fy, cx, cy;

@@ -229,20 +229,18 @@ __device__ __forceinline__ bool project_emit(const FrameDev& F, uint32_t i, floa
             rgb[ch] = fmaxf(s, 0.0f);
         }
     }
-    float4* rec = splat + (g0 + i) * 3;
+    // a culled Gaussian gets only its depth key, which marks it: no later
+    // stage reads its record or footprint
     if (keep) {
+        float4* rec = splat + (g0 + i) * 3;
         // exponent of alpha in base 2: A dx^2 + B dx dy + C dy^2 + log2(alpha_c)
         const double nhl2e = -0.72134752044448170368;  // -log2(e) / 2
         const float C = (float)(nhl2e * p.c);
         rec[0] = make_float4((float)p.u, (float)p.v, (float)(nhl2e * p.a), (float)(2.0 * nhl2e * p.b));
         rec[1] = make_float4(C, log2f(ac), rgb[0], rgb[1]);
         rec[2] = make_float4(rgb[2], 16.0f * C, ac, (float)p.x[2]);
-    } else {
-        rec[0] = make_float4(0.f, 0.f, 0.f, 0.f);
-        rec[1] = make_float4(0.f, 0.f, 0.f, 0.f);
-        rec[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+        rect[g0 + i] = make_uint4(rx0 | (ry0 << 16), rx1 | (ry1 << 16), trims.x, trims.y);
     }
-    rect[g0 + i] = make_uint4(rx0 | (ry0 << 16), rx1 | (ry1 << 16), trims.x, trims.y);
     depth_key[g0 + i] = keep ? __float_as_uint((float)p.x[2]) : kCulled;
     return keep;
 }

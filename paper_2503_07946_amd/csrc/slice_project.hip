@@ -105,11 +105,13 @@ __global__ __launch_bounds__(kBlock, 3) void k_slice_project(const FrameDev* __r
                 float mc[3], cv[6], ac;
                 slice_outputs(S, W, mu_p, cv32, cv_fin, alpha, mc, cv, ac, flag);
                 const size_t g0 = F.g0;
+                if (F.keep_sliced) {  // uniform over the block
 #pragma unroll
-                for (int a = 0; a < 3; ++a) mu_c[3 * g0 + (size_t)a * n + i] = mc[a];
+                    for (int a = 0; a < 3; ++a) mu_c[3 * g0 + (size_t)a * n + i] = mc[a];
 #pragma unroll
-                for (int e = 0; e < 6; ++e) cov_c[6 * g0 + (size_t)e * n + i] = cv[e];
-                alpha_c[g0 + i] = ac;
+                    for (int e = 0; e < 6; ++e) cov_c[6 * g0 + (size_t)e * n + i] = cv[e];
+                    alpha_c[g0 + i] = ac;
+                }
                 keep = project_emit(F, i, ac, mc, cv, ShLds{s_sh}, splat, rect, depth_key);
             }
             wave_flags(flag, counts, f);

@@ -81,6 +81,7 @@ class FrameIO:
     dL_dimage: torch.Tensor | None = None
     grads: dict | None = None
     ncontrib: torch.Tensor | None = None
+    keep_sliced: bool = False   # keep the sliced statistics in the workspace
 
 
 @dataclass
@@ -183,7 +184,7 @@ class Renderer:
             pass
 
     # ---- batch construction ------------------------------------------------
-    def make_frames(self, items, outputs=None, need_grad=False, count=False) -> list:
+    def make_frames(self, items, outputs=None, need_grad=False, count=False, keep_sliced=False) -> list:
         frames = []
         dev = torch.device("cuda", self.device)
         for k, (scene, view) in enumerate(items):
@@ -194,7 +195,7 @@ class Renderer:
                 img = torch.empty((3, H, W), dtype=torch.float32, device=dev)
                 T = torch.empty((H, W), dtype=torch.float32, device=dev)
                 last = torch.empty((H, W), dtype=torch.int32, device=dev)
-            fr = FrameIO(scene, view, img, T, last)
+            fr = FrameIO(scene, view, img, T, last, keep_sliced=keep_sliced)
             if count:
                 fr.ncontrib = torch.empty((H, W), dtype=torch.int32, device=dev)
             if need_grad:
@@ -206,12 +207,17 @@ class Renderer:
     def cstruct(frames):
         arr = (L.Sd7Frame * len(frames))()
         for i, fr in enumerate(frames):
+            if getattr(fr, "sliced_in_ws", None) is None:
+                # whether a render with these descriptors keeps the sliced
+                # statistics the reverse pass reads
+                fr.sliced_in_ws = fr.keep_sliced or fr.grads is not None
             c = arr[i]
             c.scene = fr.scene.sd7()
             c.view = view_struct(fr.view)
             c.image, c.final_T, c.last = _ptr(fr.image), _ptr(fr.final_T), _ptr(fr.last)
             c.dL_dimage = _ptr(fr.dL_dimage)
             c.ncontrib = _ptr(fr.ncontrib)
+            c.outputs = L.SD7_OUT_SLICED if fr.keep_sliced else 0
             if fr.grads is not None:
                 c.grad = L.Sd7SceneGrad(*(_ptr(fr.grads[k]) for k in PARAMS), _ptr(fr.grads.get("lambda")))
         return arr
@@ -278,11 +284,17 @@ class Renderer:
         L.check(self.lib.sd7_render_static(self.ctx, cs, len(frames), int(capacity), _ptr(counts_out),
                                            ctypes.c_void_p(st.cuda_stream)))
 
-    def render(self, scene: GaussianScene, view, capacity=None, stream=None, count=False) -> Batch:
-        return self.render_frames(self.make_frames([(scene, view)], count=count), capacity, stream)
+    def render(self, scene: GaussianScene, view, capacity=None, stream=None, count=False,
+               keep_sliced=True) -> Batch:
+        return self.render_frames(self.make_frames([(scene, view)], count=count, keep_sliced=keep_sliced),
+                                  capacity, stream)
 
     def backward(self, b: Batch, dL_dimages, stream=None):
         """Reverse pass of a rendered batch: returns per-frame gradient dicts."""
+        for fr in b.frames:
+            if not fr.sliced_in_ws:
+                raise RuntimeError("the batch was rendered without its sliced statistics: render with "
+                                   "keep_sliced=True (or gradient buffers) before the reverse pass")
         for fr, g in zip(b.frames, dL_dimages):
             fr.dL_dimage = g.contiguous()
             if fr.grads is None:
@@ -398,14 +410,14 @@ def get_renderer(device=None) -> Renderer:
 
 class Render7DGS(torch.autograd.Function):
     """image = render(mu_p, mu_t, mu_d, L, alpha, sh; view).  The backward runs
-    the library's reverse kernels (compositing recomputed front to back, no
-    per-pixel list state saved)."""
+    the library's reverse kernels (compositing recomputed back to front from
+    each pixel's final transmittance, no per-pixel list state saved)."""
 
     @staticmethod
     def forward(ctx, mu_p, mu_t, mu_d, L_, alpha, sh, view):
         r = get_renderer(mu_p.device.index)
         scene = GaussianScene(*(t.detach().contiguous() for t in (mu_p, mu_t, mu_d, L_, alpha, sh)))
-        b = r.render_frames(r.make_frames([(scene, view)]))
+        b = r.render_frames(r.make_frames([(scene, view)], keep_sliced=True))
         ctx.batch = b
         ctx.renderer = r
         return b.frames[0].image

@@ -192,8 +192,8 @@ class Scheduler:
 
 
 def run_plain(executor, requests, realtime: bool = True, clock=time.perf_counter) -> ServeStats:
-    """Baseline: one request at a time in arrival order, each rendered with its
-    exact pair count (one host sync per frame), on the same kernels."""
+    """Baseline: one request at a time in arrival order, each rendered by one
+    call and waited for before the next starts, on the same kernels."""
     t0 = clock()
     done = []
     for r in sorted(requests, key=lambda q: q.arrival):
@@ -294,10 +294,21 @@ class GpuExecutor:
         return out
 
     def render_one(self, r: Request):
-        """Plain path: one frame, exact pair count (one host sync)."""
-        b = self.R.render_frames(self.R.make_frames([(self.scenes[r.scene], r.view)]),
-                                 capacity=self.pair_estimate(r), exact=True)
-        self.torch.cuda.current_stream().synchronize()
+        """Plain path: one frame in one sd7_render call with the pair count
+        learned for its (scene, resolution), then one wait for its counters;
+        if the arena overflowed it is rendered again with the exact count."""
+        from . import _lib as L
+        frames = self.R.make_frames([(self.scenes[r.scene], r.view)])
+        cap = (self.pair_estimate(r) + PAIR_ROUND - 1) // PAIR_ROUND * PAIR_ROUND
+        b = self.R.batch(frames, cap)
+        self.R.stage("sd7_render", b)
+        c = self.R.read_counts(b)
+        need = int(c[0, L.SD7_CNT_NEEDED])
+        key = (r.scene, r.view.W, r.view.H)
+        self.est[key] = max(self.est.get(key, 0), need)
+        if c[0, L.SD7_CNT_FLAGS] & L.SD7_FLAG_PAIR_OVERFLOW:
+            b = self.R.render_frames(frames, capacity=need, exact=True)
+            self.torch.cuda.current_stream().synchronize()
         if self.keep:
             fr = b.frames[0]
             return (fr.image.cpu(), fr.final_T.cpu(), fr.last.cpu())

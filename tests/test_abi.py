@@ -36,14 +36,15 @@ def test_struct_sizes_match_the_header_layout():
     # sd7_view: 16 floats, 2 int32, t, d[3], 2 lambdas, bg[3], d_per_gaussian -> 112 bytes
     assert ctypes.sizeof(L.Sd7View) == 112
     assert ctypes.sizeof(L.Sd7Scene) == 64
-    assert ctypes.sizeof(L.Sd7Frame) == 64 + 112 + 4 * 8 + 7 * 8 + 8
+    assert ctypes.sizeof(L.Sd7Frame) == 64 + 112 + 4 * 8 + 7 * 8 + 8 + 8   # outputs + padding
 
 
 def test_constants_match_the_header():
     from paper_2503_07946_amd import serve
     defines = dict(re.findall(r"#define (SD7_[A-Z_]+) \(?(-?\d+)u?\)?", open(HEADER).read()))
     for name in ("SD7_MAX_FRAMES", "SD7_TILE", "SD7_PAIR_ROUND", "SD7_CNT_KEPT", "SD7_CNT_PAIRS",
-                 "SD7_CNT_PAIR_BASE", "SD7_CNT_FLAGS", "SD7_CNT_NEEDED", "SD7_CNT_WORDS", "SD7_AGR_WEIGHTS"):
+                 "SD7_CNT_PAIR_BASE", "SD7_CNT_FLAGS", "SD7_CNT_NEEDED", "SD7_CNT_WORDS", "SD7_AGR_WEIGHTS",
+                 "SD7_OUT_SLICED"):
         assert int(defines[name]) == getattr(L, name), name
     assert serve.PAIR_ROUND == L.SD7_PAIR_ROUND
 

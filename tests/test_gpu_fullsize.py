@@ -40,7 +40,7 @@ def c1_batch(R, c1):
     scene, views = c1
     gs = GaussianScene.from_host(scene)
     print("[fullsize] 200k Gaussians, batch of 25 x 800x800", flush=True)
-    b = R.render_frames(R.make_frames([(gs, v) for v in views]))
+    b = R.render_frames(R.make_frames([(gs, v) for v in views], keep_sliced=True))
     torch.cuda.synchronize()
     return b
 
@@ -113,7 +113,7 @@ def test_c1_agr_batch_slice_and_crop(R, c1, report):
     w = scenegen.agr_weights(1)
     gs = GaussianScene.from_host(scene, agr=w)
     print("[fullsize] AGR: 200k Gaussians, batch of 25 x 800x800", flush=True)
-    b = R.render_frames(R.make_frames([(gs, v) for v in views]))
+    b = R.render_frames(R.make_frames([(gs, v) for v in views], keep_sliced=True))
     torch.cuda.synchronize()
     f = len(views) - 1
     v = views[f]
@@ -204,6 +204,7 @@ def test_c4_slice_and_integer_stage(R, c4, report):
     dk = b.depth_key().cpu().numpy().view(np.uint32)
     rect = b.rect().cpu().numpy().view(np.uint32)
     kept = dk != 0xFFFFFFFF
+    rect[~kept] = 0   # culled Gaussians have no footprint
     gi, ry, ra, rb = footprint_rows(rect)
     live = kept[gi] & (rb > ra)
     gi, ry, ra, rb = gi[live], ry[live], ra[live], rb[live]
@@ -246,7 +247,7 @@ def test_c4_64_views_forward_backward_and_centre_crops(R, c4, report):
     for s0 in range(0, len(views), C4_INFLIGHT):
         vb = views[s0:s0 + C4_INFLIGHT]
         print(f"[fullsize] c4 views {s0}..{s0 + len(vb) - 1}: forward", flush=True)
-        b = R.render_frames(R.make_frames([(gs, v) for v in vb]))
+        b = R.render_frames(R.make_frames([(gs, v) for v in vb], keep_sliced=True))
         c = b.counts().cpu().numpy()
         assert not np.any(c[:, 3] & 4), "pair arena overflow"
         pairs += c[:, 1].tolist()

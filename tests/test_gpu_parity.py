@@ -108,6 +108,7 @@ def test_footprint_holds_every_reached_tile(R, case, report):
     dk = b.depth_key().cpu().numpy().view(np.uint32)
     rect = b.rect().cpu().numpy().view(np.uint32)
     use = (dk != CULLED) & pr.visible & ~flag
+    rect[dk == CULLED] = 0   # culled Gaussians have no footprint
     gi, ty, a, bb = footprint_rows(rect)
     sel = use[gi]
     gi, ty, a, bb = gi[sel], ty[sel], a[sel], bb[sel]
