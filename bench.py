@@ -465,24 +465,30 @@ def small_bench(R, L, reps: int = 300):
     scene, views = scenegen.config0()
     gs = GaussianScene.from_host(scene)
     c = R.read_counts(R.render(gs, views[0]))
-    b = R.batch(R.make_frames([(gs, views[0])]), int(c[0, L.SD7_CNT_NEEDED]) + L.SD7_PAIR_ROUND)
-    for _ in range(20):
-        R.stage("sd7_render", b)
-    torch.cuda.synchronize()
-    lat = []
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        R.stage("sd7_render", b)
+    cap = int(c[0, L.SD7_CNT_NEEDED]) + L.SD7_PAIR_ROUND
+    frames = R.make_frames([(gs, views[0])])
+    b = R.batch(frames, cap)
+    G = R.graph(frames, cap)
+    out = {"workload": "1,000 7D Gaussians, one 64x64 view per call"}
+    for name, call in (("graph", lambda: G.launch()), ("eager", lambda: R.stage("sd7_render", b))):
+        for _ in range(20):
+            call()
         torch.cuda.synchronize()
-        lat.append(1e6 * (time.perf_counter() - t0))
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        R.stage("sd7_render", b)
-    torch.cuda.synchronize()
-    return {"workload": "1,000 7D Gaussians, one 64x64 view per call",
-            "latency_us_p50": round(float(np.percentile(lat, 50)), 1),
-            "latency_us_p99": round(float(np.percentile(lat, 99)), 1),
-            "back_to_back_us_per_frame": round(1e6 * (time.perf_counter() - t0) / reps, 1)}
+        lat = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            call()
+            torch.cuda.synchronize()
+            lat.append(1e6 * (time.perf_counter() - t0))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            call()
+        torch.cuda.synchronize()
+        out[name] = {"latency_us_p50": round(float(np.percentile(lat, 50)), 1),
+                     "latency_us_p99": round(float(np.percentile(lat, 99)), 1),
+                     "back_to_back_us_per_frame": round(1e6 * (time.perf_counter() - t0) / reps, 1)}
+    G.close()
+    return out
 
 
 def cpu_model() -> str:
@@ -679,16 +685,23 @@ def main():
             R.stage("sd7_render", b)
             torch.cuda.synchronize()
             lat_batched += [1e3 * (time.perf_counter() - s0)] * b.nf
-    # plain: one frame per sd7_render call with the pair count learned for this
-    # scene and resolution (no read-back inside the frame), waited for
-    lat_plain = []
+    # plain: one frame per call with the pair count learned for this scene and
+    # resolution (no read-back inside the frame), waited for; replayed as a
+    # captured HIP graph (sd7_graph_launch), and as eager sd7_render calls
+    lat_plain, lat_plain_eager = [], []
     cap1 = int(max(pairs) * 1.05) + L.SD7_PAIR_ROUND
+    G = R.graph(R.make_frames([(gs, views[0])]), cap1)
     for v in views[:a.plain_frames]:
+        s0 = time.perf_counter()
+        G.launch(R.make_frames([(gs, v)]))
+        torch.cuda.synchronize()
+        lat_plain.append(1e3 * (time.perf_counter() - s0))
         s0 = time.perf_counter()
         bp = R.batch(R.make_frames([(gs, v)]), cap1)
         R.stage("sd7_render", bp)
         torch.cuda.synchronize()
-        lat_plain.append(1e3 * (time.perf_counter() - s0))
+        lat_plain_eager.append(1e3 * (time.perf_counter() - s0))
+    G.close()
     plain_fps = len(lat_plain) / (sum(lat_plain) / 1e3) if lat_plain else None
 
     small = small_bench(R, L) if a.small else None
@@ -712,7 +725,10 @@ def main():
                    "batch": a.batch, "streams": a.streams, "parallelism": "single GPU"},
         "mpixel_per_s": round(fps * W * H / 1e6, 1),
         "latency_ms": {"batched_p50": pct(lat_batched, 50), "batched_p99": pct(lat_batched, 99),
-                       "plain_p50": pct(lat_plain, 50), "plain_p99": pct(lat_plain, 99)},
+                       "plain_p50": pct(lat_plain, 50), "plain_p99": pct(lat_plain, 99),
+                       "plain_eager_p50": pct(lat_plain_eager, 50), "plain_eager_p99": pct(lat_plain_eager, 99),
+                       "plain": "one frame per call, waited for: a replayed HIP graph of the render "
+                                "(eager: one sd7_render call)"},
         "plain_fps": round(plain_fps, 2) if plain_fps else None,
         "stage_ms_per_step": per_step_stage,
         "pairs_per_view_mean": int(np.mean(pairs)), "kept_per_view_mean": int(np.mean(kept)),

@@ -355,6 +355,27 @@ sd7_status sd7_rasterize(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t 
 sd7_status sd7_render(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t pair_capacity,
                       void* ws, size_t ws_bytes, sd7_stream stream);
 
+/* Replayed renders (Sec. 4.4 render path as one HIP graph).  A request loop
+ * that renders frames of the same sizes again and again (one frame per call,
+ * say) spends most of a small frame's time launching its ~30 kernels.
+ * sd7_graph_create captures the kernel launches of sd7_render for these
+ * frames, this pair capacity and this workspace (which the graph keeps
+ * using: it must outlive the graph) into one HIP graph; nothing is launched
+ * at creation.  sd7_graph_launch uploads the frames' descriptors to the
+ * workspace and replays the graph on `stream`: views, scene arrays and
+ * output pointers may differ from the captured frames, but the number of
+ * frames, each frame's Gaussian count and resolution, whether it counts
+ * contributors or carries AGR weights, and which frames share a scene (the
+ * same arrays) must not (SD7_EINVAL otherwise).  The
+ * outputs are bitwise those of sd7_render.  Launches of one graph share its
+ * workspace: on different streams they must be ordered by the caller.
+ * sd7_graph_destroy frees the graph (not the workspace). */
+typedef struct sd7_graph sd7_graph;
+sd7_status sd7_graph_create(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t pair_capacity, void* ws,
+                            size_t ws_bytes, sd7_graph** out);
+sd7_status sd7_graph_launch(sd7_graph* graph, const sd7_frame* frames, int nf, sd7_stream stream);
+void sd7_graph_destroy(sd7_graph* graph);
+
 /* For callers that cannot allocate device memory: code under HIP graph
  * capture, serving loops that must not call hipMalloc, harnesses that forbid
  * it.  sd7_render over a workspace the library owns instead of one the caller

@@ -75,7 +75,8 @@ STAGES = ("sd7_slice", "sd7_project", "sd7_slice_project", "sd7_bin", "sd7_raste
           "sd7_rasterize_backward", "sd7_project_backward", "sd7_slice_backward")
 EXPORTS = ("sd7_create", "sd7_destroy", "sd7_last_error", "sd7_plan", "sd7_read_counts",
            "sd7_cov_decompose", "sd7_split_test", "sd7_adam_step", "sd7_prune_workspace_size",
-           "sd7_prune_count", "sd7_prune_apply", "sd7_render_static") + STAGES
+           "sd7_prune_count", "sd7_prune_apply", "sd7_render_static", "sd7_graph_create",
+           "sd7_graph_launch", "sd7_graph_destroy") + STAGES
 
 
 class Sd7Error(RuntimeError):
@@ -118,6 +119,13 @@ def load(path: str = LIB_PATH):
         fn.restype = ctypes.c_int32
     L.sd7_render_static.argtypes = [P, ctypes.POINTER(Sd7Frame), ctypes.c_int, ctypes.c_int64, P, P]
     L.sd7_render_static.restype = ctypes.c_int32
+    L.sd7_graph_create.argtypes = [P, ctypes.POINTER(Sd7Frame), ctypes.c_int, ctypes.c_int64, P, ctypes.c_size_t,
+                                   ctypes.POINTER(P)]
+    L.sd7_graph_create.restype = ctypes.c_int32
+    L.sd7_graph_launch.argtypes = [P, ctypes.POINTER(Sd7Frame), ctypes.c_int, P]
+    L.sd7_graph_launch.restype = ctypes.c_int32
+    L.sd7_graph_destroy.argtypes = [P]
+    L.sd7_graph_destroy.restype = None
     L.sd7_read_counts.argtypes = [P, ctypes.c_int, P, ctypes.POINTER(ctypes.c_uint32), P]
     L.sd7_read_counts.restype = ctypes.c_int32
     L.sd7_cov_decompose.argtypes = [P, ctypes.c_int64, P, P, P, P]

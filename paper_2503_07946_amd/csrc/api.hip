@@ -341,10 +341,10 @@ struct Call {
     T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
 
-sd7_status begin(sd7_ctx* ctx, const sd7_frame* fr, int nf, int64_t cap, void* ws, size_t ws_bytes,
-                 sd7_stream stream, Call& c, bool need_bwd)
+// Plan the call and set up its launch state (no device work).
+sd7_status prepare(sd7_ctx* ctx, const sd7_frame* fr, int nf, int64_t cap, void* ws, size_t ws_bytes,
+                   sd7_stream stream, Call& c, bool need_bwd)
 {
-    g_err[0] = 0;
     if (!ctx) return fail(SD7_EINVAL, "ctx is NULL");
     if (!ws) return fail(SD7_EINVAL, "workspace is NULL");
     sd7_status s = make_plan(fr, nf, cap, c.P, need_bwd);
@@ -364,6 +364,15 @@ sd7_status begin(sd7_ctx* ctx, const sd7_frame* fr, int nf, int64_t cap, void* w
         c.agr = c.agr || fr[f].scene.agr != nullptr;
     }
     if (need_bwd && c.agr) return fail(SD7_EINVAL, "the reverse calls do not support AGR scenes");
+    return SD7_OK;
+}
+
+sd7_status begin(sd7_ctx* ctx, const sd7_frame* fr, int nf, int64_t cap, void* ws, size_t ws_bytes,
+                 sd7_stream stream, Call& c, bool need_bwd)
+{
+    g_err[0] = 0;
+    sd7_status s = prepare(ctx, fr, nf, cap, ws, ws_bytes, stream, c, need_bwd);
+    if (s != SD7_OK) return s;
     return upload_table(ctx, fr, nf, c.P, c.ws, c.st);
 }
 
@@ -717,6 +726,140 @@ STAGE(sd7_render, false, {
     return do_raster(c);
 })
 STAGE(sd7_rasterize_backward, true, { return do_raster_bwd(c); })
+
+}  // extern "C"
+
+struct sd7_graph {
+    sd7_ctx* ctx = nullptr;
+    Plan P;
+    char* ws = nullptr;
+    int nf = 0;
+    int64_t cap = 0;
+    bool count = false, agr = false;
+    int64_t n[SD7_MAX_FRAMES];
+    int32_t W[SD7_MAX_FRAMES], H[SD7_MAX_FRAMES];
+    bool has_count[SD7_MAX_FRAMES], has_agr[SD7_MAX_FRAMES];
+    int same_as[SD7_MAX_FRAMES];  // first frame with the same scene arrays
+    hipGraphExec_t exec = nullptr;
+};
+
+// For each frame, the first frame of the call with the same scene (the same
+// six parameter arrays and n): the grouping the fused slice/projection's
+// launch is planned on.
+void scene_sharing(const sd7_frame* fr, int nf, int* same_as)
+{
+    for (int f = 0; f < nf; ++f) {
+        same_as[f] = f;
+        const sd7_scene& A = fr[f].scene;
+        for (int h = 0; h < f; ++h) {
+            const sd7_scene& B = fr[h].scene;
+            if (A.n == B.n && A.mu_p == B.mu_p && A.mu_t == B.mu_t && A.mu_d == B.mu_d && A.L == B.L &&
+                A.alpha == B.alpha && A.sh == B.sh) {
+                same_as[f] = h;
+                break;
+            }
+        }
+    }
+}
+
+extern "C" {
+
+sd7_status sd7_graph_create(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t cap, void* ws, size_t ws_bytes,
+                            sd7_graph** out)
+{
+    g_err[0] = 0;
+    if (!out) return fail(SD7_EINVAL, "out is NULL");
+    *out = nullptr;
+    Call c;
+    sd7_status s = prepare(ctx, frames, nf, cap, ws, ws_bytes, nullptr, c, false);
+    if (s != SD7_OK) return s;
+    sd7_graph* g = new (std::nothrow) sd7_graph();
+    if (!g) return fail(SD7_ENOMEM, "out of host memory");
+    g->ctx = ctx;
+    g->P = c.P;
+    g->ws = c.ws;
+    g->nf = nf;
+    g->cap = cap;
+    g->count = c.count;
+    g->agr = c.agr;
+    for (int f = 0; f < nf; ++f) {
+        g->n[f] = frames[f].scene.n;
+        g->W[f] = frames[f].view.W;
+        g->H[f] = frames[f].view.H;
+        g->has_count[f] = frames[f].ncontrib != nullptr;
+        g->has_agr[f] = frames[f].scene.agr != nullptr;
+    }
+    scene_sharing(frames, nf, g->same_as);
+    // capture the render's launches (kernels only: the clears are fill
+    // kernels) on a private stream of default priority
+    hipStream_t st = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete g;
+        return fail(SD7_EHIP, "hipStreamCreateWithFlags: %s", hipGetErrorString(e));
+    }
+    c.st = st;
+    hipGraph_t graph = nullptr;
+    e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        s = do_slice_project(c);
+        if (s == SD7_OK) s = do_bin(c);
+        if (s == SD7_OK) s = do_raster(c);
+        const hipError_t e2 = hipStreamEndCapture(st, &graph);
+        if (s == SD7_OK && e2 != hipSuccess) s = fail(SD7_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+    } else {
+        s = fail(SD7_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    }
+    if (s == SD7_OK) {
+        e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) s = fail(SD7_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(st);
+    if (s != SD7_OK) {
+        delete g;
+        return s;
+    }
+    *out = g;
+    return SD7_OK;
+}
+
+sd7_status sd7_graph_launch(sd7_graph* g, const sd7_frame* frames, int nf, sd7_stream stream)
+{
+    g_err[0] = 0;
+    if (!g || !frames) return fail(SD7_EINVAL, "graph or frames is NULL");
+    if (nf != g->nf) return fail(SD7_EINVAL, "nf=%d, the graph was captured for %d frames", nf, g->nf);
+    int same_as[SD7_MAX_FRAMES];
+    scene_sharing(frames, nf, same_as);
+    for (int f = 0; f < nf; ++f) {
+        if (same_as[f] != g->same_as[f])
+            return fail(SD7_EINVAL, "frame %d: frames share scenes differently from the captured frames", f);
+        const sd7_frame& F = frames[f];
+        if (F.scene.n != g->n[f] || F.view.W != g->W[f] || F.view.H != g->H[f] ||
+            (F.ncontrib != nullptr) != g->has_count[f] || (F.scene.agr != nullptr) != g->has_agr[f])
+            return fail(SD7_EINVAL, "frame %d: Gaussian count, resolution, contributor counts or AGR differ "
+                        "from the captured frame", f);
+        if (F.scene.n > 0 && (!F.scene.mu_p || !F.scene.mu_t || !F.scene.mu_d || !F.scene.L || !F.scene.alpha ||
+                              !F.scene.sh))
+            return fail(SD7_EINVAL, "frame %d: NULL scene array", f);
+        if (!F.image || !F.final_T || !F.last) return fail(SD7_EINVAL, "frame %d: NULL image/final_T/last", f);
+        if (!(F.view.fx > 0.f) || !(F.view.fy > 0.f)) return fail(SD7_EINVAL, "frame %d: focal length must be > 0", f);
+    }
+    HIP_TRY(hipSetDevice(g->ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    sd7_status s = upload_table(g->ctx, frames, nf, g->P, g->ws, st);
+    if (s != SD7_OK) return s;
+    HIP_TRY(hipGraphLaunch(g->exec, st));
+    return SD7_OK;
+}
+
+void sd7_graph_destroy(sd7_graph* g)
+{
+    if (!g) return;
+    (void)hipSetDevice(g->ctx->device);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    delete g;
+}
 
 sd7_status sd7_render_static(sd7_ctx* ctx, const sd7_frame* frames, int nf, int64_t cap, uint32_t* counts_out,
                              sd7_stream stream)

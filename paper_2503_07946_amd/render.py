@@ -273,6 +273,11 @@ class Renderer:
         self.stage("sd7_rasterize", b, stream)
         return b
 
+    def graph(self, frames, capacity: int) -> "RenderGraph":
+        """sd7_render of frames of these sizes captured as one HIP graph
+        (sd7_graph_create), with its own workspace."""
+        return RenderGraph(self, frames, capacity)
+
     def render_static(self, frames, capacity: int, counts_out: torch.Tensor | None = None, stream=None):
         """sd7_render over the library's own per-device workspace (no workspace
         argument; nothing is allocated).  counts_out: optional int32 device
@@ -305,6 +310,44 @@ class Renderer:
         for s in ("sd7_rasterize_backward", "sd7_project_backward", "sd7_slice_backward"):
             self.stage(s, b, stream)
         return [fr.grads for fr in b.frames]
+
+
+class RenderGraph:
+    """A captured sd7_render (include/sd7.h, sd7_graph_*): launch() replays it
+    for frames of the captured sizes (other views, scenes of the same size,
+    other outputs).  Owns the workspace the graph uses."""
+
+    def __init__(self, renderer: Renderer, frames, capacity: int):
+        self.R = renderer
+        self.b = renderer.batch(frames, capacity)
+        h = ctypes.c_void_p()
+        L.check(renderer.lib.sd7_graph_create(renderer.ctx, self.b.cstruct, self.b.nf, int(capacity),
+                                              ctypes.c_void_p(self.b.ws.data_ptr()), self.b.ws.numel(),
+                                              ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self, frames=None, stream=None) -> Batch:
+        """Replay for `frames` (default: the captured ones); returns the batch
+        view of the workspace with these frames."""
+        st = torch.cuda.current_stream(self.R.device) if stream is None else stream
+        cs, nf = self.b.cstruct, self.b.nf
+        if frames is not None:
+            cs, nf = self.R.cstruct(frames), len(frames)
+        L.check(self.R.lib.sd7_graph_launch(self.handle, cs, nf, ctypes.c_void_p(st.cuda_stream)))
+        if frames is not None:
+            self.b.frames, self.b.cstruct = frames, cs
+        return self.b
+
+    def close(self):
+        if self.handle:
+            self.R.lib.sd7_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 _RENDERERS: dict = {}

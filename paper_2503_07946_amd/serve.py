@@ -299,12 +299,12 @@ class GpuExecutor:
         if the arena overflowed it is rendered again with the exact count."""
         from . import _lib as L
         frames = self.R.make_frames([(self.scenes[r.scene], r.view)])
+        key = (r.scene, r.view.W, r.view.H)
         cap = (self.pair_estimate(r) + PAIR_ROUND - 1) // PAIR_ROUND * PAIR_ROUND
         b = self.R.batch(frames, cap)
         self.R.stage("sd7_render", b)
         c = self.R.read_counts(b)
         need = int(c[0, L.SD7_CNT_NEEDED])
-        key = (r.scene, r.view.W, r.view.H)
         self.est[key] = max(self.est.get(key, 0), need)
         if c[0, L.SD7_CNT_FLAGS] & L.SD7_FLAG_PAIR_OVERFLOW:
             b = self.R.render_frames(frames, capacity=need, exact=True)
