@@ -246,7 +246,7 @@ sd7_status make_plan(const sd7_frame* fr, int nf, int64_t cap, Plan& P, bool nee
     S.pt_a = take(4 * CR);
     S.pt_b = take(4 * CR);
     S.pg_b = take(4 * CR);
-    S.toff = take(4 * (N + 16));
+    S.toff = take(4 * (P.counting ? 0 : N + 16));
     S.srect = take(16 * (P.counting ? N : 0));
     S.sspan = take(4 * (P.counting ? N : 0));
     S.segs_all = take(sizeof(SortSeg) * nf);
@@ -520,28 +520,20 @@ sd7_status do_bin(const Call& c)
     if ((s = radix_pass(c, false, ka, va, kb, order, segs_kept, tot_kept, mw, 8)) != SD7_OK) return s;
     if ((s = radix_pass(c, false, kb, order, ka, va, segs_kept, tot_kept, mw, 16)) != SD7_OK) return s;
     if ((s = radix_pass(c, false, ka, va, kb, order, segs_kept, tot_kept, mw, 24)) != SD7_OK) return s;
-    // tiles per sorted Gaussian -> exclusive offsets
-    uint32_t* toff = c.at<uint32_t>(S.toff);
-    if (c.P.gblocks) {
-        k_gather_ntiles<<<c.P.gblocks, kBlock, 0, c.st>>>(c.tab, c.P.gmap, c.counts, order,
-                                                          c.at<uint4>(L.off_rect), toff,
-                                                          c.P.counting ? c.at<uint4>(S.srect) : nullptr,
-                                                          c.P.counting ? c.at<uint32_t>(S.sspan) : nullptr);
-        LAUNCH_CHECK("k_gather_ntiles");
-    }
-    const uint32_t ntot = (uint32_t)L.n_total;
-    if ((s = fill(c, words, 1, 0)) != SD7_OK) return s;
-    if (ntot && (s = scan(c, toff, ntot, nullptr, ntot, words)) != SD7_OK) return s;
-    k_setup_pairs<<<1, 64, 0, c.st>>>(c.tab, nf, ntot, toff, words, (uint32_t)L.pair_capacity, c.counts,
-                                      segs_pairs, tot_pairs);
-    LAUNCH_CHECK("k_setup_pairs");
     if (c.P.counting) {
-        // counting binner: [chunk][tile] counts -> per-tile prefix over chunks and
-        // tile totals -> scan of the totals -> placement -> ranges
+        // counting binner: depth-sorted boxes -> [chunk][tile] counts -> per-tile
+        // prefix over chunks and tile totals -> scan of the totals (which also
+        // gives each frame's pair count) -> arena -> placement -> ranges
         uint32_t* cnt = c.at<uint32_t>(c.P.cnt);
         uint32_t* ttot = c.at<uint32_t>(c.P.ttot);
-        const uint4* srect = c.at<uint4>(S.srect);
+        uint4* srect = c.at<uint4>(S.srect);
         const uint32_t ttiles = (uint32_t)L.tiles_total;
+        if (c.P.gblocks) {
+            k_gather_boxes<<<c.P.gblocks, kBlock, 0, c.st>>>(c.tab, c.P.gmap, c.counts, order,
+                                                             c.at<uint4>(L.off_rect), srect,
+                                                             c.at<uint32_t>(S.sspan));
+            LAUNCH_CHECK("k_gather_boxes");
+        }
         if (c.P.kblocks) {
             k_tile_count<<<c.P.kblocks, 256, sizeof(uint32_t) * c.P.max_tiles, c.st>>>(c.tab, c.P.kmap, c.counts,
                                                                                       srect, cnt);
@@ -549,7 +541,11 @@ sd7_status do_bin(const Call& c)
         }
         k_tile_colscan<<<c.P.rblocks, 256, 0, c.st>>>(c.tab, c.P.rmap, cnt, ttot);
         LAUNCH_CHECK("k_tile_colscan");
-        if ((s = scan(c, ttot, ttiles, nullptr, ttiles, nullptr)) != SD7_OK) return s;
+        if ((s = fill(c, words, 1, 0)) != SD7_OK) return s;
+        if ((s = scan(c, ttot, ttiles, nullptr, ttiles, words)) != SD7_OK) return s;
+        k_setup_pairs<<<1, 64, 0, c.st>>>(c.tab, nf, ttiles, true, ttot, words, (uint32_t)L.pair_capacity,
+                                          c.counts, segs_pairs, tot_pairs);
+        LAUNCH_CHECK("k_setup_pairs");
         if (c.P.cblocks) {
             k_group_place<<<c.P.cblocks, 64, 0, c.st>>>(c.tab, c.P.cmap, c.counts, order, srect,
                                                          c.at<uint32_t>(S.sspan), cnt, ttot,
@@ -560,6 +556,19 @@ sd7_status do_bin(const Call& c)
         LAUNCH_CHECK("k_tile_ranges");
         return SD7_OK;
     }
+    // tiles per sorted Gaussian -> exclusive offsets
+    uint32_t* toff = c.at<uint32_t>(S.toff);
+    if (c.P.gblocks) {
+        k_gather_ntiles<<<c.P.gblocks, kBlock, 0, c.st>>>(c.tab, c.P.gmap, c.counts, order,
+                                                          c.at<uint4>(L.off_rect), toff);
+        LAUNCH_CHECK("k_gather_ntiles");
+    }
+    const uint32_t ntot = (uint32_t)L.n_total;
+    if ((s = fill(c, words, 1, 0)) != SD7_OK) return s;
+    if (ntot && (s = scan(c, toff, ntot, nullptr, ntot, words)) != SD7_OK) return s;
+    k_setup_pairs<<<1, 64, 0, c.st>>>(c.tab, nf, ntot, false, toff, words, (uint32_t)L.pair_capacity, c.counts,
+                                      segs_pairs, tot_pairs);
+    LAUNCH_CHECK("k_setup_pairs");
     if ((s = fill(c, c.at<uint32_t>(L.off_ranges), 2 * (size_t)L.tiles_total, 0)) != SD7_OK) return s;
     // emit so that the last tile-sort pass lands in the pair_g array
     uint32_t* pt_a = c.at<uint32_t>(S.pt_a);

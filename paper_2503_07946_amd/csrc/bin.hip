@@ -430,42 +430,48 @@ __device__ __forceinline__ bool span_meets(uint32_t d, uint32_t gx, uint32_t gy)
     return (gx - (d & 0xFFu) <= ((d >> 8) & 0xFFu)) & (gy - ((d >> 16) & 0xFFu) <= (d >> 24));
 }
 
-// Tiles of each Gaussian's footprint in depth order (0 past the kept ones)
-// and, when srect is given, the binner boxes and group spans of the
-// footprints in depth order (empty past the kept ones).
+// Tiles of each Gaussian's footprint in depth order (0 past the kept ones).
 __global__ __launch_bounds__(kBlock) void k_gather_ntiles(const FrameDev* __restrict__ tab, BlockMap bm,
                                                           const uint32_t* __restrict__ counts,
                                                           const uint32_t* __restrict__ order,
                                                           const uint4* __restrict__ rect,
-                                                          uint32_t* __restrict__ ntiles,
-                                                          uint4* __restrict__ srect,
-                                                          uint32_t* __restrict__ sspan)
+                                                          uint32_t* __restrict__ ntiles)
 {
     const int f = frame_of_block(bm, blockIdx.x);
     const FrameDev& F = tab[f];
     const uint32_t j = (blockIdx.x - bm.start[f]) * kBlock + threadIdx.x;
     if (j >= F.n) return;
     const uint32_t kept = counts[f * SD7_CNT_WORDS + SD7_CNT_KEPT];
-    uint32_t nt = 0;
-    uint4 r = make_uint4(0u, 0u, 0u, 0u);
-    if (j < kept) {
-        r = rect[F.g0 + order[F.g0 + j]];
-        nt = Footprint(r).tiles();
-    }
-    ntiles[F.g0 + j] = nt;
-    if (srect) {
-        srect[F.g0 + j] = bin_box(r);
-        sspan[F.g0 + j] = group_span(r);
-    }
+    ntiles[F.g0 + j] = j < kept ? Footprint(rect[F.g0 + order[F.g0 + j]]).tiles() : 0u;
+}
+
+// The binner boxes and group spans of the kept footprints in depth order.
+__global__ __launch_bounds__(kBlock) void k_gather_boxes(const FrameDev* __restrict__ tab, BlockMap bm,
+                                                         const uint32_t* __restrict__ counts,
+                                                         const uint32_t* __restrict__ order,
+                                                         const uint4* __restrict__ rect,
+                                                         uint4* __restrict__ srect,
+                                                         uint32_t* __restrict__ sspan)
+{
+    const int f = frame_of_block(bm, blockIdx.x);
+    const FrameDev& F = tab[f];
+    const uint32_t j = (blockIdx.x - bm.start[f]) * kBlock + threadIdx.x;
+    if (j >= counts[f * SD7_CNT_WORDS + SD7_CNT_KEPT]) return;
+    const uint4 r = rect[F.g0 + order[F.g0 + j]];
+    srect[F.g0 + j] = bin_box(r);
+    sspan[F.g0 + j] = group_span(r);
 }
 
 // Per-frame pair counts, arena slots (each frame's share rounded up to a whole
-// number of sort work tiles) and the tile-sort segments.  One wave, lane f =
-// frame f: the frames' pair counts are read in parallel; the arena is then
-// handed out in frame order (a frame that does not fit gets none, and later
-// frames may still fit), a walk over values already in registers.
-__global__ __launch_bounds__(64) void k_setup_pairs(const FrameDev* __restrict__ tab, int nf, uint32_t n_total,
-                                                    const uint32_t* __restrict__ toff,
+// number of sort work tiles) and the tile-sort segments.  The pair counts come
+// from an exclusive scan over all frames of the tiles per sorted Gaussian
+// (by_tiles false) or of the pairs per tile (by_tiles true), each frame's
+// elements contiguous.  One wave, lane f = frame f: the frames' pair counts
+// are read in parallel; the arena is then handed out in frame order (a frame
+// that does not fit gets none, and later frames may still fit), a walk over
+// values already in registers.
+__global__ __launch_bounds__(64) void k_setup_pairs(const FrameDev* __restrict__ tab, int nf, uint32_t len_total,
+                                                    bool by_tiles, const uint32_t* __restrict__ toff,
                                                     const uint32_t* __restrict__ toff_total, uint32_t capacity,
                                                     uint32_t* __restrict__ counts, SortSeg* __restrict__ segs,
                                                     SortTotals* __restrict__ tot)
@@ -475,9 +481,10 @@ __global__ __launch_bounds__(64) void k_setup_pairs(const FrameDev* __restrict__
     const uint32_t total = *toff_total;
     uint32_t P = 0, lo = 0;
     if (live) {
-        const uint32_t g0 = tab[lane].g0, n = tab[lane].n;
-        lo = g0 < n_total ? toff[g0] : total;
-        const uint32_t hi = (g0 + n) < n_total ? toff[g0 + n] : total;
+        const FrameDev& F = tab[lane];
+        const uint32_t e0 = by_tiles ? F.t0 : F.g0, ne = by_tiles ? F.tiles_x * F.tiles_y : F.n;
+        lo = e0 < len_total ? toff[e0] : total;
+        const uint32_t hi = (e0 + ne) < len_total ? toff[e0 + ne] : total;
         P = hi - lo;
     }
     uint32_t base = 0, wt = 0, excl = 0;
@@ -503,7 +510,7 @@ __global__ __launch_bounds__(64) void k_setup_pairs(const FrameDev* __restrict__
         c[SD7_CNT_PAIRS] = my_len;
         c[SD7_CNT_NEEDED] = P;
         c[SD7_CNT_PAIR_BASE] = my_base;
-        c[5] = lo;  // scan value at the frame's first Gaussian
+        c[5] = lo;  // scan value at the frame's first element
         SortSeg sg;
         sg.in_base = my_base; sg.out_base = my_base; sg.len = my_len; sg.wt0 = my_wt;
         sg.nwt = (my_len + kSortItems - 1) / kSortItems; sg.cnt_excl = my_excl; sg.pad[0] = sg.pad[1] = 0;
@@ -678,9 +685,8 @@ constexpr int kWaitLgkm0 = 0xC07F;
 constexpr int kBufferWord3 = 0x00020000;
 
 // One block (256 lanes) per (frame, chunk) writes the chunk's row of the
-// count matrix (zeros for a frame whose pairs overflowed).  Per-row difference
-// array over the frame's tiles in LDS: a footprint whose row y spans tiles
-// [a, b) adds +1 at (a, y) and -1 at (b, y).
+// count matrix.  Per-row difference array over the frame's tiles in LDS: a
+// footprint whose row y spans tiles [a, b) adds +1 at (a, y) and -1 at (b, y).
 __global__ __launch_bounds__(256) void k_tile_count(const FrameDev* __restrict__ tab, BlockMap cm,
                                                     const uint32_t* __restrict__ counts,
                                                     const uint4* __restrict__ srect,
@@ -693,29 +699,25 @@ __global__ __launch_bounds__(256) void k_tile_count(const FrameDev* __restrict__
     const uint32_t tx = F.tiles_x, T = F.tiles_x * F.tiles_y;
     for (uint32_t i = threadIdx.x; i < T; i += 256) s_d[i] = 0;
     __syncthreads();
-    const uint32_t* cf = counts + f * SD7_CNT_WORDS;
-    const bool live = !(cf[SD7_CNT_FLAGS] & SD7_FLAG_PAIR_OVERFLOW);
     const uint32_t kept = frame_kept(counts, f);
     const uint32_t j0 = chunk_begin(kept, F.nch, c), j1 = chunk_begin(kept, F.nch, c + 1);
-    if (live) {
-        for (uint32_t j = j0 + threadIdx.x; j < j1; j += 256) {
-            const uint4 bb = srect[F.g0 + j];
-            const Footprint fp(make_uint4(bb.x & ~kMaskFlag, bb.y, bb.z, bb.w));
-            if (!(bb.x & kMaskFlag) && !fp.trimmed()) {
-                for (uint32_t y = fp.y0; y < fp.y1; ++y) {
-                    atomicAdd(&s_d[y * tx + fp.x0], 1u);
-                    if (fp.x1 < tx) atomicSub(&s_d[y * tx + fp.x1], 1u);
-                }
-                continue;
+    for (uint32_t j = j0 + threadIdx.x; j < j1; j += 256) {
+        const uint4 bb = srect[F.g0 + j];
+        const Footprint fp(make_uint4(bb.x & ~kMaskFlag, bb.y, bb.z, bb.w));
+        if (!(bb.x & kMaskFlag) && !fp.trimmed()) {
+            for (uint32_t y = fp.y0; y < fp.y1; ++y) {
+                atomicAdd(&s_d[y * tx + fp.x0], 1u);
+                if (fp.x1 < tx) atomicSub(&s_d[y * tx + fp.x1], 1u);
             }
-            for (uint32_t r = 0; r < fp.h(); ++r) {
-                int a, b;
-                bin_box_row(bb, r, a, b);
-                if (a >= b) continue;
-                const uint32_t y = fp.y0 + r;
-                atomicAdd(&s_d[y * tx + a], 1u);
-                if ((uint32_t)b < tx) atomicSub(&s_d[y * tx + b], 1u);
-            }
+            continue;
+        }
+        for (uint32_t r = 0; r < fp.h(); ++r) {
+            int a, b;
+            bin_box_row(bb, r, a, b);
+            if (a >= b) continue;
+            const uint32_t y = fp.y0 + r;
+            atomicAdd(&s_d[y * tx + a], 1u);
+            if ((uint32_t)b < tx) atomicSub(&s_d[y * tx + b], 1u);
         }
     }
     __syncthreads();
