@@ -92,11 +92,11 @@ def lib():
         L.ora_fp32_model.restype = None
         L.ora_composite.argtypes = [i64, P, P, P, P, P, P, i64, P, ctypes.POINTER(OraView),
                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                    ctypes.POINTER(OraFlagCfg), P, P, P, P, P, P, P]
+                                    ctypes.POINTER(OraFlagCfg), P, P, P, P, P, P, P, P]
         L.ora_composite.restype = ctypes.c_int
         L.ora_render.argtypes = [i64, P, P, P, P, P, P, ctypes.POINTER(OraView),
                                  ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                 ctypes.POINTER(OraFlagCfg), P, P, P, P, P, P, P]
+                                 ctypes.POINTER(OraFlagCfg), P, P, P, P, P, P, P, P]
         L.ora_render.restype = ctypes.c_int
         L.ora_sh_basis.argtypes = [ctypes.c_double] * 3 + [P]
         L.ora_agr_encoding.argtypes = [ctypes.c_double, P]
@@ -252,6 +252,7 @@ class Image:
     flags: np.ndarray     # [h][w] uint32 ORA_FLAG_* bits
     fbound: np.ndarray    # [h][w] bound on the pixel's change from in-band decisions
     ntest: np.ndarray     # [h][w] Gaussians tested by the pixel's brute-force loop
+    vbound: np.ndarray    # [h][w] bound on its change from opacities moving within their bands
 
 
 FLAG_ALPHA, FLAG_T, FLAG_DEPTH = 1, 2, 4
@@ -273,38 +274,40 @@ def composite(sliced: Sliced, proj: Projected, view, crop=None, flags=None, band
     ordv = np.ascontiguousarray(order(proj))
     img = np.zeros((3, h, w)); T = np.zeros((h, w)); nc = np.zeros((h, w), np.int32)
     ch = np.zeros((h, w), np.uint64); fl = np.zeros((h, w), np.uint32); fb = np.zeros((h, w))
-    nt = np.zeros((h, w), np.int64)
+    nt = np.zeros((h, w), np.int64); vb = np.zeros((h, w))
     fc = flagcfg(**(flags or {}))
     ep = fp32_model(sliced, view) if banded else None
     ov = ora_view(view)
     lib().ora_composite(n, _p(proj.mean2d), _p(proj.conic), _p(np.ascontiguousarray(sliced.alpha_c)),
                         _p(proj.depth), _p(proj.rgb), _p(ep) if ep is not None else None, len(ordv),
                         _p(ordv), ctypes.byref(ov), x0, y0, w, h, ctypes.byref(fc) if banded else None,
-                        _p(img), _p(T), _p(nc), _p(ch), _p(fl), _p(fb), _p(nt))
-    return Image(img, T, nc, ch, fl, fb, nt)
+                        _p(img), _p(T), _p(nc), _p(ch), _p(fl), _p(fb), _p(nt), _p(vb))
+    return Image(img, T, nc, ch, fl, fb, nt, vb)
 
 
 def render(scene, view, crop=None, flags=None, agr_weights=None, banded=True) -> Image:
     """Full FP64 forward of one view (optionally a pixel crop x0, y0, w, h),
     with the scene first refined by AGR when weights are given.  banded:
-    also flag in-band decisions and bound their effect (flags, fbound)."""
+    also flag in-band decisions and bound their effect (flags, fbound), and
+    bound the effect of every contributor's opacity moving within its band
+    (vbound)."""
     if agr_weights is not None:
         scene = agr(scene, view.t, agr_weights)
     x0, y0, w, h = crop if crop is not None else (0, 0, view.W, view.H)
     n = scene.n
     img = np.zeros((3, h, w)); T = np.zeros((h, w)); nc = np.zeros((h, w), np.int32)
     ch = np.zeros((h, w), np.uint64); fl = np.zeros((h, w), np.uint32); fb = np.zeros((h, w))
-    nt = np.zeros((h, w), np.int64)
+    nt = np.zeros((h, w), np.int64); vb = np.zeros((h, w))
     fc = flagcfg(**(flags or {}))
     arrs = [_f64(scene.mu_p), _f64(scene.mu_t), _f64(scene.mu_d), _f64(scene.L),
             _f64(scene.alpha), _f64(scene.sh)]
     ov = ora_view(view)
     rc = lib().ora_render(n, *[_p(a) for a in arrs], ctypes.byref(ov), x0, y0, w, h,
                           ctypes.byref(fc) if banded else None, _p(img), _p(T), _p(nc), _p(ch), _p(fl), _p(fb),
-                          _p(nt))
+                          _p(nt), _p(vb))
     if rc != 0:
         raise MemoryError("oracle render failed to allocate")
-    return Image(img, T, nc, ch, fl, fb, nt)
+    return Image(img, T, nc, ch, fl, fb, nt, vb)
 
 
 def sh_basis(x: float, y: float, z: float) -> np.ndarray:

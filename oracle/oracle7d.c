@@ -456,11 +456,26 @@ typedef struct {
 } ora_event;
 #define ORA_MAX_EVENTS 32
 
+/* Band of ln alpha of Gaussian g at a pixel at offset (dx, dy) from its mean
+ * (the model described with ora_flagcfg). */
+static double band_lnalpha(int64_t n, int64_t g, const double* mean2d, const double* errpar,
+                           const ora_flagcfg* fc, double ca, double cb, double cc, double dx, double dy)
+{
+    const double E = ldexp(1.0, -24);
+    const double w0 = ca * dx + cb * dy, w1 = cb * dx + cc * dy;
+    const double aw0 = fabs(w0), aw1 = fabs(w1);
+    const double qabs = ca * dx * dx + 2.0 * fabs(cb * dx * dy) + cc * dy * dy;
+    const double squad = aw0 * aw0 * errpar[n + g] + 2.0 * aw0 * aw1 * errpar[2 * n + g] +
+                         aw1 * aw1 * errpar[3 * n + g];
+    return E * (fc->k_mu * (aw0 + aw1) * errpar[g] + fc->k_uv * (aw0 * fabs(mean2d[g]) + aw1 * fabs(mean2d[n + g])) +
+                fc->k_s * 0.5 * squad + fc->k_eval * (8.0 + 0.5 * qabs) + fc->k_ac);
+}
+
 int ora_composite(int64_t n, const double* mean2d, const double* conic, const double* alpha_c,
                   const double* depth, const double* rgb, const double* errpar, int64_t m,
                   const int64_t* order, const ora_view* v, int x0, int y0, int w, int h,
                   const ora_flagcfg* fc, double* image, double* final_T, int32_t* ncontrib,
-                  uint64_t* chash, uint32_t* flags, double* fbound, int64_t* ntest)
+                  uint64_t* chash, uint32_t* flags, double* fbound, int64_t* ntest, double* vbound)
 {
     const double bg[3] = {v->bg[0], v->bg[1], v->bg[2]};
     const int64_t npx = (int64_t)w * h;
@@ -499,14 +514,7 @@ int ora_composite(int64_t n, const double* mean2d, const double* conic, const do
                 const double a = araw < ALPHA_MAX ? araw : ALPHA_MAX;
                 double ea = 0.0;   /* band of ln alpha at this (Gaussian, pixel) */
                 if (banded) {
-                    const double w0 = ca * dx + cb * dy, w1 = cb * dx + cc * dy;
-                    const double aw0 = fabs(w0), aw1 = fabs(w1);
-                    const double qabs = ca * dx * dx + 2.0 * fabs(cb * dx * dy) + cc * dy * dy;
-                    const double squad = aw0 * aw0 * errpar[n + g] + 2.0 * aw0 * aw1 * errpar[2 * n + g] +
-                                         aw1 * aw1 * errpar[3 * n + g];
-                    ea = E * (fc->k_mu * (aw0 + aw1) * errpar[g] +
-                              fc->k_uv * (aw0 * fabs(mean2d[g]) + aw1 * fabs(mean2d[n + g])) +
-                              fc->k_s * 0.5 * squad + fc->k_eval * (8.0 + 0.5 * qabs) + fc->k_ac);
+                    ea = band_lnalpha(n, g, mean2d, errpar, fc, ca, cb, cc, dx, dy);
                     if (fabs(log(araw / ALPHA_MIN)) < ea) {
                         ora_event e = {a < ALPHA_MIN ? 0 : 1, a < ALPHA_MIN ? ALPHA_MIN * exp(ea) : a, T,
                                        {C[0], C[1], C[2]}, {0, 0, 0}};
@@ -581,7 +589,39 @@ int ora_composite(int64_t n, const double* mean2d, const double* conic, const do
                 fb += d;
                 if (d > fc->impact_min) fl_imp |= e->kind <= 1 ? ORA_FLAG_ALPHA : ORA_FLAG_T;
             }
+            /* value band: first-order change of the pixel when each
+             * contributor's ln alpha moves by its band (decisions kept):
+             * d C / d ln a_i = a_i (T_i rgb_i - rest_i), rest_i the colour
+             * behind it divided by (1 - a_i); a clamped alpha only moves
+             * when its band reaches below the clamp */
+            double vb = 0.0;
+            if (banded && vbound) {
+                double Tv = 1.0, Cv[3] = {0, 0, 0};
+                for (int64_t jj = 0; jj < j && jj < m; ++jj) {
+                    const int64_t g = order[jj];
+                    const double dx = mean2d[g] - pxc, dy = mean2d[n + g] - pyc;
+                    const double ca = conic[g], cb = conic[n + g], cc = conic[2 * n + g];
+                    const double q = ca * dx * dx + 2.0 * cb * dx * dy + cc * dy * dy;
+                    const double araw = alpha_c[g] * exp(-0.5 * q);
+                    const double a = araw < ALPHA_MAX ? araw : ALPHA_MAX;
+                    if (a < ALPHA_MIN) continue;
+                    const double ea = band_lnalpha(n, g, mean2d, errpar, fc, ca, cb, cc, dx, dy);
+                    if (araw < ALPHA_MAX * exp(ea)) {
+                        double d = 0.0;
+                        for (int ch = 0; ch < 3; ++ch) {
+                            const double c = rgb[(int64_t)ch * n + g];
+                            const double rest = (img[ch] - Cv[ch] - a * Tv * c) / (1.0 - a);
+                            const double x = fabs(a * (Tv * c - rest));
+                            if (x > d) d = x;
+                        }
+                        vb += ea * d;
+                    }
+                    for (int ch = 0; ch < 3; ++ch) Cv[ch] += rgb[(int64_t)ch * n + g] * a * Tv;
+                    Tv *= 1.0 - a;
+                }
+            }
             for (int ch = 0; ch < 3; ++ch) image[ch * npx + p] = img[ch];
+            if (vbound) vbound[p] = banded ? 1.01 * vb : 0.0;
             if (final_T) final_T[p] = T;
             if (ncontrib) ncontrib[p] = nc;
             if (chash) chash[p] = hsh;
@@ -648,7 +688,7 @@ int ora_render(int64_t n, const double* mu_p, const double* mu_t, const double* 
                const double* L, const double* alpha, const double* sh, const ora_view* v,
                int x0, int y0, int w, int h, const ora_flagcfg* fc,
                double* image, double* final_T, int32_t* ncontrib, uint64_t* chash,
-               uint32_t* flags, double* fbound, int64_t* ntest)
+               uint32_t* flags, double* fbound, int64_t* ntest, double* vbound)
 {
     double* mu_c = (double*)malloc(sizeof(double) * 3 * n + 8);
     double* cov_c = (double*)malloc(sizeof(double) * 6 * n + 8);
@@ -671,7 +711,7 @@ int ora_render(int64_t n, const double* mu_p, const double* mu_t, const double* 
         int64_t m = ora_order(n, depth, vis, order);
         if (errpar) ora_fp32_model(n, mu_c, cov_c, v, errpar);
         ora_composite(n, mean2d, conic, alpha_c, depth, rgb, errpar, m, order, v, x0, y0, w, h, fc,
-                      image, final_T, ncontrib, chash, flags, fbound, ntest);
+                      image, final_T, ncontrib, chash, flags, fbound, ntest, vbound);
     }
     free(mu_c); free(cov_c); free(alpha_c); free(mean2d); free(conic);
     free(depth); free(rgb); free(rect); free(vis); free(order); free(errpar);

@@ -90,19 +90,23 @@ void ora_fp32_model(int64_t n, const double* mu_c, const double* cov_c, const or
  * 1.01 x the sum over all in-band decisions of their first-order effect on the
  * pixel (max over channels) if taken the other way, 0 where there is none.
  * ntest (optional) [h][w]: the Gaussians the pixel's loop tested (the
- * stopping one included), the brute force's unit of work. */
+ * stopping one included), the brute force's unit of work.  vbound (optional,
+ * banded only) [h][w]: 1.01 x the sum over the pixel's contributors of
+ * |d C / d ln alpha_i| (max over channels) times alpha_i's band, the
+ * first-order change of the pixel when every contributor's opacity moves
+ * within its FP32 band with every decision kept (0 without fc). */
 int ora_composite(int64_t n, const double* mean2d, const double* conic, const double* alpha_c,
                   const double* depth, const double* rgb, const double* errpar, int64_t m,
                   const int64_t* order, const ora_view* v, int x0, int y0, int w, int h,
                   const ora_flagcfg* fc, double* image, double* final_T, int32_t* ncontrib,
-                  uint64_t* chash, uint32_t* flags, double* fbound, int64_t* ntest);
+                  uint64_t* chash, uint32_t* flags, double* fbound, int64_t* ntest, double* vbound);
 
 /* slice + project + order + composite (fc NULL: no flags, fbound 0). */
 int ora_render(int64_t n, const double* mu_p, const double* mu_t, const double* mu_d,
                const double* L, const double* alpha, const double* sh, const ora_view* v,
                int x0, int y0, int w, int h, const ora_flagcfg* fc,
                double* image, double* final_T, int32_t* ncontrib, uint64_t* chash,
-               uint32_t* flags, double* fbound, int64_t* ntest);
+               uint32_t* flags, double* fbound, int64_t* ntest, double* vbound);
 
 /* Adaptive Gaussian refinement (Sec. 4.3).  wts: the four MLPs in the order
  * p, t, d, l, each as W1[64][27] (row-major), b1[64], W2[C_out][64], b2[C_out]

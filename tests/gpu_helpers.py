@@ -100,13 +100,16 @@ def oracle_rect_flags(sl, pr, view, eps=1e-4):
 
 
 def image_check(gpu_img, ora, tol=1e-4):
-    """Every pixel is compared: |gpu - oracle| <= tol + fbound, where fbound is
-    the oracle's bound on the first-order change of the pixel should an FP32
-    evaluation take one of its in-band decisions (opacity test, stop, depth
-    order) the other way (0 on pixels without such a decision).  Returns (max
-    over all pixels of |gpu - oracle| - fbound, number of flagged pixels)."""
+    """Every pixel is compared: |gpu - oracle| <= tol + fbound + vbound, where
+    fbound is the oracle's bound on the first-order change of the pixel should
+    an FP32 evaluation take one of its in-band decisions (opacity test, stop,
+    depth order) the other way (0 on pixels without such a decision), and
+    vbound its bound on the first-order change when every contributor's
+    opacity moves within its FP32 band (decisions kept).  Returns (max over
+    all pixels of |gpu - oracle| - fbound - vbound, number of flagged
+    pixels)."""
     err = np.abs(gpu_img.astype(np.float64) - ora.image).max(0)
-    return float((err - ora.fbound).max()), int((ora.flags != 0).sum())
+    return float((err - ora.fbound - ora.vbound).max()), int((ora.flags != 0).sum())
 
 
 def grad_entry_error(gpu: np.ndarray, ora: np.ndarray) -> np.ndarray:

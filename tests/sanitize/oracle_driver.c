@@ -71,19 +71,20 @@ int main(void)
     uint64_t* chash = (uint64_t*)calloc(px, sizeof(uint64_t));
     uint32_t* flags = (uint32_t*)calloc(px, sizeof(uint32_t));
     int64_t* ntest = (int64_t*)calloc(px, sizeof(int64_t));
+    double* vbound = alloc(px);
     int rc = ora_composite(n, mean2d, conic, alpha_c, depth, rgb, errpar, m, order, &v, 0, 0, v.W, v.H, &fc,
-                           image, final_T, ncon, chash, flags, fbound, ntest);
+                           image, final_T, ncon, chash, flags, fbound, ntest, vbound);
     /* a crop at the bottom-right border, without flags */
     rc |= ora_composite(n, mean2d, conic, alpha_c, depth, rgb, NULL, m, order, &v, v.W - 7, v.H - 5, 7, 5, NULL,
-                        image, final_T, ncon, chash, flags, fbound, ntest);
+                        image, final_T, ncon, chash, flags, fbound, ntest, NULL);
     /* the whole path per Gaussian direction, two threads then one */
     v.d_mode = 1;
     ora_set_num_threads(2);
     rc |= ora_render(n, mu_p, mu_t, mu_d, L, alpha, sh, &v, 3, 2, 20, 17, &fc, image, final_T, ncon, chash, flags,
-                     fbound, ntest);
+                     fbound, ntest, vbound);
     ora_set_num_threads(1);
     rc |= ora_render(0, mu_p, mu_t, mu_d, L, alpha, sh, &v, 0, 0, v.W, v.H, NULL, image, final_T, ncon, NULL, NULL,
-                     NULL, NULL);
+                     NULL, NULL, NULL);
     /* adaptive refinement with seeded weights */
     double* wts = alloc(AGR_WEIGHTS);
     for (int k = 0; k < AGR_WEIGHTS; ++k) wts[k] = 0.2 * (urand() - 0.5);
@@ -100,7 +101,7 @@ int main(void)
     free(mu_p); free(mu_t); free(mu_d); free(L); free(alpha); free(sh);
     free(mu_c); free(cov_c); free(alpha_c); free(ft); free(fd); free(status);
     free(mean2d); free(conic); free(depth); free(rgb); free(box); free(rect); free(vis); free(order); free(errpar);
-    free(image); free(final_T); free(fbound); free(ncon); free(chash); free(flags); free(ntest);
+    free(image); free(final_T); free(fbound); free(ncon); free(chash); free(flags); free(ntest); free(vbound);
     free(wts); free(r_mu_p); free(r_mu_t); free(r_mu_d); free(r_L);
     return (bad < 1 || nv < 1 || nv >= n || m != nv || rc != 0) ? 1 : 0;
 }

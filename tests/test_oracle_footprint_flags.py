@@ -248,12 +248,81 @@ def test_depth_flag_fires_on_near_ties_and_bounds_the_swap():
             assert not (im.flags & oracle.FLAG_DEPTH).any()
 
 
+# ---- value band: opacities moving within their bands, decisions kept -----
+
+# only the constant term of the band: ln alpha's band is 1e-3 at every
+# (Gaussian, pixel), whatever the geometry
+CONST_BAND = dict(k_mu=0.0, k_uv=0.0, k_s=0.0, k_eval=0.0, k_ac=1e-3 * 2.0 ** 24, k_T=0.0, k_z=0.0)
+
+
+def test_value_band_of_one_splat_is_its_opacity_derivative_times_the_band():
+    """One splat over the background: C = a rgb + (1 - a) bg, so
+    d C / d ln a = a (rgb - bg) and the value bound is 1.01 x 1e-3 x a
+    max|rgb - bg|.  Scaling the splat's opacity by e^(+-1e-3) (every decision
+    kept) moves the pixel by that much to first order."""
+    v = axis_view(W=32, H=32, z0=3.0, bg=(0.2, 0.4, 0.6))
+    dc = (1.5, -0.5, 0.2)
+    rgb = np.maximum(0.0, 0.5 + np.float32(dc).astype(np.float64) * Y00)
+    bg = np.array([0.2, 0.4, 0.6], np.float32).astype(np.float64)
+    sc = _iso([0.3], [0.0], [0.5], [dc])
+    im = oracle.render(sc, v, flags=CONST_BAND)
+    for px, py in ((16, 16), (19, 14), (21, 17)):
+        a_pix, _ = _alpha_at(v, sc, 0, px, py)
+        assert oracle.ALPHA_MIN * 1.01 < a_pix < oracle.ALPHA_MAX
+        assert im.vbound[py, px] == pytest.approx(1.01 * 1e-3 * a_pix * np.abs(rgb - bg).max(), rel=1e-9)
+        for sgn in (1.0, -1.0):
+            moved = oracle.render(_iso([0.3], [0.0], [0.5 * math.exp(sgn * 1e-3)], [dc]), v, banded=False)
+            d = np.abs(moved.image[:, py, px] - im.image[:, py, px]).max()
+            assert im.vbound[py, px] / 1.01 * (1 - 2e-3) <= d <= im.vbound[py, px]
+    # no contributor, no value bound
+    assert im.vbound[0, 0] == 0.0 and im.ncontrib[0, 0] == 0
+
+
+def test_value_band_of_two_splats_sums_both_derivatives():
+    """Two splats in depth order at one pixel: C = a1 c1 + (1 - a1)(a2 c2 +
+    (1 - a2) bg), so d C / d ln a1 = a1 (c1 - a2 c2 - (1 - a2) bg) and
+    d C / d ln a2 = (1 - a1) a2 (c2 - bg); the bound is 1.01 x 1e-3 x the sum
+    of their largest channels."""
+    v = axis_view(W=24, H=24, z0=3.0, bg=(1.0, 0.5, 0.0))
+    dcs = [(1.0, 0.0, -1.0), (-1.0, 1.0, 0.5)]
+    sc = _iso([0.2, 0.25], [0.0, 0.1], [0.6, 0.7], dcs)
+    im = oracle.render(sc, v, flags=CONST_BAND)
+    px, py = 13, 11
+    a1, _ = _alpha_at(v, sc, 0, px, py)
+    a2, _ = _alpha_at(v, sc, 1, px, py)
+    c1, c2 = (np.maximum(0.0, 0.5 + np.float32(d).astype(np.float64) * Y00) for d in dcs)
+    bg = np.array([1.0, 0.5, 0.0])
+    d1 = np.abs(a1 * (c1 - a2 * c2 - (1 - a2) * bg)).max()
+    d2 = np.abs((1 - a1) * a2 * (c2 - bg)).max()
+    assert im.vbound[py, px] == pytest.approx(1.01 * 1e-3 * (d1 + d2), rel=1e-9)
+
+
+def test_value_band_bounds_any_opacity_moves_within_the_band():
+    """A random scene with the constant band: scaling every Gaussian's
+    opacity by e^(s_i 1e-3), s_i = +-1 at random, moves each pixel by at most
+    fbound + vbound (decisions taken the other way are in fbound)."""
+    sc = scenegen.make_scene(400, 41, h=1.0, sigma_off=0.1)
+    v = scenegen.make_views(1, 41, r=3.0, W=48, H=40, bg=(0.3, 0.6, 0.9))[0]
+    im = oracle.render(sc, v, flags=CONST_BAND)
+    assert (im.vbound > 0).mean() > 0.5
+    rng = np.random.default_rng(7)
+    for _ in range(3):
+        s = rng.choice([-1.0, 1.0], size=sc.n)
+        sc2 = scene_from(sc.mu_p.T, sc.mu_t, sc.mu_d.T, scenegen.unpack_L(sc.L.T.astype(np.float64)),
+                         sc.alpha.astype(np.float64) * np.exp(s * 1e-3), sc.sh.T)
+        moved = oracle.render(sc2, v, banded=False)
+        d = np.abs(moved.image - im.image).max(0)
+        assert np.all(d <= im.fbound + im.vbound + 1e-12)
+        # and the bound is not loose by orders of magnitude
+        assert d.max() >= 0.05 * (im.fbound + im.vbound).max()
+
+
 def test_unbanded_render_has_no_flags_and_the_same_image():
     sc, views = scenegen.config0()
     a = oracle.render(sc, views[0])
     b = oracle.render(sc, views[0], banded=False)
     np.testing.assert_array_equal(a.image, b.image)
-    assert not b.flags.any() and not b.fbound.any()
+    assert not b.flags.any() and not b.fbound.any() and not b.vbound.any()
 
 
 def test_fp32_model_scales_on_axis():
