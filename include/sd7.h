@@ -243,9 +243,33 @@ typedef struct {
     int64_t tile0[SD7_MAX_FRAMES];
 } sd7_layout;
 
-/* Context on HIP device `device`.  *out is set on success. */
+/* Context on HIP device `device`.  *out is set on success.  With the
+ * environment variable SD7_PROFILE set (to anything but "0") when the context
+ * is created, every stage the context runs (each stage call, and the three
+ * stages inside sd7_render and sd7_render_static; not captured graphs) is
+ * timed between two HIP events on its stream; sd7_profile_read returns the
+ * totals.  The event pool (256 pairs) is made here, so timing allocates
+ * nothing later; when every pair is in flight the oldest is waited for. */
 sd7_status sd7_create(int device, sd7_ctx** out);
 void sd7_destroy(sd7_ctx* ctx);
+
+/* Per-stage GPU time of a context created with SD7_PROFILE set (Sec. 4.4's
+ * stages: slice, project, slice_project, bin, rasterize and the three reverse
+ * stages).  name: a static string; calls: stage runs; total_ms / max_ms: sum
+ * and largest of their event-to-event times. */
+typedef struct {
+    const char* name;
+    uint64_t calls;
+    double total_ms;
+    double max_ms;
+} sd7_stage_time;
+
+/* Host only; blocks until every timed stage has run.  Writes up to `max`
+ * entries, one per stage that ran at least once, in pipeline order, and sets
+ * *count to the number written (0 for a context without SD7_PROFILE).
+ * reset != 0 clears the totals afterwards.  SD7_EINVAL for a NULL ctx or
+ * count, a negative max, or a NULL out with max > 0. */
+sd7_status sd7_profile_read(sd7_ctx* ctx, sd7_stage_time* out, int max, int* count, int reset);
 
 /* Densification helper (Algorithm 1's optional step; Sec. 4.4): for n
  * symmetric 3x3 covariances cov[6][n] (packed xx, xy, xz, yy, yz, zz, e.g.

@@ -62,6 +62,11 @@ _OFFS = ["off_table", "off_counts", "off_mu_c", "off_cov_c", "off_alpha_c", "off
          "off_d_splat", "off_d_mu_c", "off_d_cov_c", "off_d_alpha_c", "off_scratch"]
 
 
+class Sd7StageTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("calls", ctypes.c_uint64), ("total_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double)]
+
+
 class Sd7Layout(ctypes.Structure):
     _fields_ = ([("bytes", ctypes.c_size_t), ("nframes", ctypes.c_int32),
                  ("tile_sort_passes", ctypes.c_int32), ("n_total", ctypes.c_int64),
@@ -76,7 +81,7 @@ STAGES = ("sd7_slice", "sd7_project", "sd7_slice_project", "sd7_bin", "sd7_raste
 EXPORTS = ("sd7_create", "sd7_destroy", "sd7_last_error", "sd7_plan", "sd7_read_counts",
            "sd7_cov_decompose", "sd7_split_test", "sd7_adam_step", "sd7_prune_workspace_size",
            "sd7_prune_count", "sd7_prune_apply", "sd7_render_static", "sd7_graph_create",
-           "sd7_graph_launch", "sd7_graph_destroy") + STAGES
+           "sd7_graph_launch", "sd7_graph_destroy", "sd7_profile_read") + STAGES
 
 
 class Sd7Error(RuntimeError):
@@ -126,6 +131,9 @@ def load(path: str = LIB_PATH):
     L.sd7_graph_launch.restype = ctypes.c_int32
     L.sd7_graph_destroy.argtypes = [P]
     L.sd7_graph_destroy.restype = None
+    L.sd7_profile_read.argtypes = [P, ctypes.POINTER(Sd7StageTime), ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                   ctypes.c_int]
+    L.sd7_profile_read.restype = ctypes.c_int32
     L.sd7_read_counts.argtypes = [P, ctypes.c_int, P, ctypes.POINTER(ctypes.c_uint32), P]
     L.sd7_read_counts.restype = ctypes.c_int32
     L.sd7_cov_decompose.argtypes = [P, ctypes.c_int64, P, P, P, P]

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -269,6 +270,13 @@ sd7_status make_plan(const sd7_frame* fr, int nf, int64_t cap, Plan& P, bool nee
 
 }  // namespace
 
+// Stages timed under SD7_PROFILE=1, in the order sd7_profile_read reports them.
+enum ProfStage { kPSlice, kPProject, kPSliceProject, kPBin, kPRaster, kPRasterBwd, kPProjectBwd, kPSliceBwd,
+                 kPStages };
+const char* const kProfNames[kPStages] = {"slice", "project", "slice_project", "bin", "rasterize",
+                                          "rasterize_backward", "project_backward", "slice_backward"};
+constexpr int kProfSlots = 256;  // (start, end) event pairs in flight
+
 struct sd7_ctx {
     int device = 0;
     char* scratch = nullptr;     // device address of this device's `scratch` array
@@ -278,6 +286,15 @@ struct sd7_ctx {
     bool used[kRing];
     int next = 0;
     std::mutex mu;
+    // per-stage timing (SD7_PROFILE=1 at creation): event pairs in a ring,
+    // slots [pf_head, pf_head + pf_n) recorded and not yet read
+    bool profile = false;
+    hipEvent_t pf_start[kProfSlots], pf_end[kProfSlots];
+    int pf_stage[kProfSlots];
+    int pf_head = 0, pf_n = 0;
+    uint64_t pf_calls[kPStages] = {};
+    double pf_total[kPStages] = {}, pf_max[kPStages] = {};
+    std::mutex pf_mu;
 };
 
 namespace {
@@ -331,6 +348,7 @@ sd7_status upload_table(sd7_ctx* ctx, const sd7_frame* fr, int nf, const Plan& P
 
 struct Call {
     Plan P;
+    sd7_ctx* ctx = nullptr;
     char* ws;
     hipStream_t st;
     const FrameDev* tab;
@@ -373,7 +391,49 @@ sd7_status begin(sd7_ctx* ctx, const sd7_frame* fr, int nf, int64_t cap, void* w
     g_err[0] = 0;
     sd7_status s = prepare(ctx, fr, nf, cap, ws, ws_bytes, stream, c, need_bwd);
     if (s != SD7_OK) return s;
+    c.ctx = ctx;
     return upload_table(ctx, fr, nf, c.P, c.ws, c.st);
+}
+
+// Adds a finished (start, end) pair to its stage's totals and frees the
+// oldest slot (the caller holds pf_mu).
+sd7_status profile_retire(sd7_ctx* ctx)
+{
+    const int k = ctx->pf_head;
+    HIP_TRY(hipEventSynchronize(ctx->pf_end[k]));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ctx->pf_start[k], ctx->pf_end[k]));
+    const int st = ctx->pf_stage[k];
+    ctx->pf_calls[st] += 1;
+    ctx->pf_total[st] += ms;
+    ctx->pf_max[st] = std::max(ctx->pf_max[st], (double)ms);
+    ctx->pf_head = (k + 1) % kProfSlots;
+    ctx->pf_n -= 1;
+    return SD7_OK;
+}
+
+// Runs one stage; with profiling on, between two events on the call's
+// stream (the oldest pair is read first when every slot is in flight).
+template <class F>
+sd7_status timed(const Call& c, ProfStage stage, F&& run)
+{
+    sd7_ctx* ctx = c.ctx;
+    if (!ctx || !ctx->profile) return run();
+    int k;
+    {
+        std::lock_guard<std::mutex> lock(ctx->pf_mu);
+        if (ctx->pf_n == kProfSlots) {
+            const sd7_status s = profile_retire(ctx);
+            if (s != SD7_OK) return s;
+        }
+        k = (ctx->pf_head + ctx->pf_n) % kProfSlots;
+        ctx->pf_n += 1;
+        ctx->pf_stage[k] = stage;
+        HIP_TRY(hipEventRecord(ctx->pf_start[k], c.st));
+    }
+    const sd7_status s = run();
+    HIP_TRY(hipEventRecord(ctx->pf_end[k], c.st));
+    return s;
 }
 
 sd7_status fill(const Call& c, void* p, size_t count, uint32_t value)
@@ -688,7 +748,57 @@ sd7_status sd7_create(int device, sd7_ctx** out)
             return fail(SD7_EHIP, "hipEventCreate: %s", hipGetErrorString(e));
         }
     }
+    const char* pf = std::getenv("SD7_PROFILE");
+    if (pf && pf[0] && std::strcmp(pf, "0") != 0) {
+        int made = 0;
+        for (; made < kProfSlots; ++made) {
+            if (hipEventCreate(&c->pf_start[made]) != hipSuccess) break;
+            if (hipEventCreate(&c->pf_end[made]) != hipSuccess) {
+                (void)hipEventDestroy(c->pf_start[made]);
+                break;
+            }
+        }
+        if (made < kProfSlots) {
+            for (int j = 0; j < made; ++j) {
+                (void)hipEventDestroy(c->pf_start[j]);
+                (void)hipEventDestroy(c->pf_end[j]);
+            }
+            for (int i = 0; i < kRing; ++i) (void)hipEventDestroy(c->ev[i]);
+            (void)hipHostFree(c->ring);
+            delete c;
+            return fail(SD7_EHIP, "hipEventCreate for SD7_PROFILE failed");
+        }
+        c->profile = true;
+    }
     *out = c;
+    return SD7_OK;
+}
+
+sd7_status sd7_profile_read(sd7_ctx* ctx, sd7_stage_time* out, int max, int* count, int reset)
+{
+    g_err[0] = 0;
+    if (!ctx || !count || (max > 0 && !out) || max < 0) return fail(SD7_EINVAL, "ctx/count/out invalid");
+    *count = 0;
+    if (!ctx->profile) return SD7_OK;
+    HIP_TRY(hipSetDevice(ctx->device));
+    std::lock_guard<std::mutex> lock(ctx->pf_mu);
+    while (ctx->pf_n > 0) {
+        const sd7_status s = profile_retire(ctx);
+        if (s != SD7_OK) return s;
+    }
+    int n = 0;
+    for (int st = 0; st < kPStages; ++st) {
+        if (ctx->pf_calls[st] == 0) continue;
+        if (n < max) out[n] = sd7_stage_time{kProfNames[st], ctx->pf_calls[st], ctx->pf_total[st], ctx->pf_max[st]};
+        ++n;
+    }
+    *count = std::min(n, max);
+    if (reset) {
+        for (int st = 0; st < kPStages; ++st) {
+            ctx->pf_calls[st] = 0;
+            ctx->pf_total[st] = ctx->pf_max[st] = 0.0;
+        }
+    }
     return SD7_OK;
 }
 
@@ -699,6 +809,13 @@ void sd7_destroy(sd7_ctx* ctx)
     for (int i = 0; i < kRing; ++i) {
         if (ctx->used[i]) (void)hipEventSynchronize(ctx->ev[i]);
         (void)hipEventDestroy(ctx->ev[i]);
+    }
+    if (ctx->profile) {
+        (void)hipDeviceSynchronize();
+        for (int k = 0; k < kProfSlots; ++k) {
+            (void)hipEventDestroy(ctx->pf_start[k]);
+            (void)hipEventDestroy(ctx->pf_end[k]);
+        }
     }
     (void)hipHostFree(ctx->ring);
     delete ctx;
@@ -724,17 +841,17 @@ sd7_status sd7_plan(const sd7_frame* frames, int nf, int64_t pair_capacity, sd7_
         __VA_ARGS__                                                                                   \
     }
 
-STAGE(sd7_slice, false, { return do_slice(c); })
-STAGE(sd7_project, false, { return do_project(c); })
-STAGE(sd7_slice_project, false, { return do_slice_project(c); })
-STAGE(sd7_bin, false, { return do_bin(c); })
-STAGE(sd7_rasterize, false, { return do_raster(c); })
+STAGE(sd7_slice, false, { return timed(c, kPSlice, [&] { return do_slice(c); }); })
+STAGE(sd7_project, false, { return timed(c, kPProject, [&] { return do_project(c); }); })
+STAGE(sd7_slice_project, false, { return timed(c, kPSliceProject, [&] { return do_slice_project(c); }); })
+STAGE(sd7_bin, false, { return timed(c, kPBin, [&] { return do_bin(c); }); })
+STAGE(sd7_rasterize, false, { return timed(c, kPRaster, [&] { return do_raster(c); }); })
 STAGE(sd7_render, false, {
-    if ((s = do_slice_project(c)) != SD7_OK) return s;
-    if ((s = do_bin(c)) != SD7_OK) return s;
-    return do_raster(c);
+    if ((s = timed(c, kPSliceProject, [&] { return do_slice_project(c); })) != SD7_OK) return s;
+    if ((s = timed(c, kPBin, [&] { return do_bin(c); })) != SD7_OK) return s;
+    return timed(c, kPRaster, [&] { return do_raster(c); });
 })
-STAGE(sd7_rasterize_backward, true, { return do_raster_bwd(c); })
+STAGE(sd7_rasterize_backward, true, { return timed(c, kPRasterBwd, [&] { return do_raster_bwd(c); }); })
 
 }  // extern "C"
 
@@ -883,17 +1000,17 @@ sd7_status sd7_render_static(sd7_ctx* ctx, const sd7_frame* frames, int nf, int6
                     c.P.L.bytes, (size_t)SD7_STATIC_WS_BYTES);
     s = begin(ctx, frames, nf, cap, ctx->scratch, SD7_STATIC_WS_BYTES, stream, c, false);
     if (s != SD7_OK) return s;
-    if ((s = do_slice_project(c)) != SD7_OK) return s;
-    if ((s = do_bin(c)) != SD7_OK) return s;
-    if ((s = do_raster(c)) != SD7_OK) return s;
+    if ((s = timed(c, kPSliceProject, [&] { return do_slice_project(c); })) != SD7_OK) return s;
+    if ((s = timed(c, kPBin, [&] { return do_bin(c); })) != SD7_OK) return s;
+    if ((s = timed(c, kPRaster, [&] { return do_raster(c); })) != SD7_OK) return s;
     if (counts_out) {
         k_copy_u32<<<1, 256, 0, c.st>>>(counts_out, c.counts, (uint32_t)(SD7_CNT_WORDS * nf));
         LAUNCH_CHECK("k_copy_u32");
     }
     return SD7_OK;
 }
-STAGE(sd7_project_backward, true, { return do_project_bwd(c); })
-STAGE(sd7_slice_backward, true, { return do_slice_bwd(c, frames, nf); })
+STAGE(sd7_project_backward, true, { return timed(c, kPProjectBwd, [&] { return do_project_bwd(c); }); })
+STAGE(sd7_slice_backward, true, { return timed(c, kPSliceBwd, [&] { return do_slice_bwd(c, frames, nf); }); })
 
 sd7_status sd7_cov_decompose(sd7_ctx* ctx, int64_t n, const float* cov, float* scale, float* rot,
                              sd7_stream stream)

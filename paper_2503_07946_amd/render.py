@@ -172,6 +172,16 @@ class Renderer:
         self.ctx = h
         self.default_capacity = 1 << 20
 
+    def profile(self, reset: bool = False) -> dict:
+        """Per-stage GPU times of this renderer's context (sd7_profile_read):
+        {stage: (calls, total_ms, max_ms)}; empty unless SD7_PROFILE was set
+        when the renderer was created.  Waits for the timed stages."""
+        out = (L.Sd7StageTime * 16)()
+        n = ctypes.c_int(0)
+        L.check(self.lib.sd7_profile_read(self.ctx, out, 16, ctypes.byref(n), int(reset)))
+        return {out[i].name.decode(): (int(out[i].calls), float(out[i].total_ms), float(out[i].max_ms))
+                for i in range(n.value)}
+
     def close(self):
         if self.ctx:
             self.lib.sd7_destroy(self.ctx)
