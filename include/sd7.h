@@ -87,6 +87,8 @@ typedef int32_t sd7_status;
 #define SD7_FLAG_NONPOS_DIAG 1u   /* some L has a diagonal entry <= 0 (Gaussian culled) */
 #define SD7_FLAG_NONFINITE 2u     /* a non-finite conditional statistic (Gaussian culled) */
 #define SD7_FLAG_PAIR_OVERFLOW 4u /* the pair arena was too small: frame not rasterized */
+#define SD7_FLAG_SORT_STALL 8u    /* a depth-sort work tile gave up waiting for the counts of an
+                                     earlier one (never expected; the frame's output is not valid) */
 
 /* per-frame device counters: SD7_CNT_WORDS uint32 words per frame */
 #define SD7_CNT_KEPT 0      /* Gaussians that survive culling */

@@ -14,6 +14,7 @@ SD7_MAX_FRAMES = 64
 SD7_TILE = 16
 SD7_PAIR_ROUND = 2048       # a frame's arena share is a multiple of this (sd7.h)
 SD7_FLAG_NONPOS_DIAG, SD7_FLAG_NONFINITE, SD7_FLAG_PAIR_OVERFLOW = 1, 2, 4
+SD7_FLAG_SORT_STALL = 8     # a depth-sort wait gave up: the frame is not valid
 SD7_OUT_SLICED = 1          # sd7_frame.outputs: keep the sliced statistics
 SD7_CNT_KEPT, SD7_CNT_PAIRS, SD7_CNT_PAIR_BASE, SD7_CNT_FLAGS = 0, 1, 2, 3
 SD7_CNT_NEEDED = 4          # pairs the frame needs (also written on overflow)

@@ -68,6 +68,8 @@ struct Scratch {
     size_t sk_a, sv_a, sk_b;         // depth sort ping-pong (keys a, vals a, keys b)
     size_t pt_a, pt_b, pg_b;         // radix tile sort: tile keys and ping-pong buffers
     size_t toff;                     // tile offsets (scan of tiles per sorted Gaussian)
+    size_t dsort, dsort_words;       // small calls' depth sort: state cleared before each sort
+    size_t dhist, dctr, dstat;       // its digit counts, tile counters, status words
     size_t srect;                    // footprints in depth order (counting binner)
     size_t sspan;                    // their tile-group spans (counting binner)
     size_t segs_all, segs_kept, segs_pairs;
@@ -87,6 +89,7 @@ struct Plan {
     uint32_t gblocks, tblocks;
     // counting binner (frames of at most kMaxCountTiles tiles)
     bool counting;
+    bool onesweep;  // depth sort with one launch per digit (calls of few work tiles)
     uint32_t max_tiles;
     uint32_t nch[SD7_MAX_FRAMES], m0[SD7_MAX_FRAMES];
     BlockMap cmap;   // one block (wave) per (frame, chunk, tile group)
@@ -99,6 +102,7 @@ struct Plan {
     size_t ttot;     // workspace offset of the per-tile totals (then their scan)
 };
 
+constexpr uint32_t kOneSweepTiles = 512;  // depth-sort work tiles up to which a call sorts one launch per digit
 constexpr uint64_t kBinWaves = 131072; // (chunk, group) waves the counting binner aims for per call
 constexpr uint64_t kMaxChunks = 512;   // chunks per frame (the depth of the per-tile column scan)
 constexpr size_t kMaxMatrix = (size_t)1 << 28;  // count-matrix entries of one call
@@ -217,6 +221,7 @@ sd7_status make_plan(const sd7_frame* fr, int nf, int64_t cap, Plan& P, bool nee
     while ((1u << bits) < max_tiles) ++bits;
     L.tile_sort_passes = std::max(1, (bits + 7) / 8);
     P.max_wt_depth = (uint32_t)wt_depth;
+    P.onesweep = P.max_wt_depth <= kOneSweepTiles;
     P.max_wt_pairs = ceil_div(cap, kSortItems) + nf;
 
     const size_t N = (size_t)ntot, T = (size_t)ttot, C = (size_t)cap;
@@ -256,8 +261,15 @@ sd7_status make_plan(const sd7_frame* fr, int nf, int64_t cap, Plan& P, bool nee
     S.tot_all = take(sizeof(SortTotals));
     S.tot_kept = take(sizeof(SortTotals));
     S.tot_pairs = take(sizeof(SortTotals));
-    P.hist_entries = 256 * (size_t)std::max(P.max_wt_depth, P.counting ? 0u : P.max_wt_pairs);
+    P.hist_entries = 256 * (size_t)std::max(P.onesweep ? 0u : P.max_wt_depth, P.counting ? 0u : P.max_wt_pairs);
     S.hist = take(4 * P.hist_entries);
+    // small calls' depth sort: digit counts [nf][4][256], tile counters [4]
+    // and status words [4][max_wt_depth][256], cleared together
+    S.dsort = off;
+    S.dhist = take(P.onesweep ? 4 * 1024 * (size_t)nf : 0);
+    S.dctr = take(P.onesweep ? 4 * 4 : 0);
+    S.dstat = take(P.onesweep ? 4 * 4 * 256 * (size_t)P.max_wt_depth : 0);
+    S.dsort_words = (off - S.dsort) / 4;
     const size_t mat = P.counting ? P.matrix_entries : 0;
     P.cnt = take(4 * mat);
     P.ttot = take(4 * (P.counting ? T + 4 : 0));
@@ -576,10 +588,32 @@ sd7_status do_bin(const Call& c)
     uint32_t* order = c.at<uint32_t>(L.off_order);
     const uint32_t* dkey = c.at<uint32_t>(L.off_depth_key);
     const uint32_t mw = c.P.max_wt_depth;
-    if ((s = radix_pass(c, true, dkey, nullptr, ka, va, segs_all, tot_all, mw, 0)) != SD7_OK) return s;
-    if ((s = radix_pass(c, false, ka, va, kb, order, segs_kept, tot_kept, mw, 8)) != SD7_OK) return s;
-    if ((s = radix_pass(c, false, kb, order, ka, va, segs_kept, tot_kept, mw, 16)) != SD7_OK) return s;
-    if ((s = radix_pass(c, false, ka, va, kb, order, segs_kept, tot_kept, mw, 24)) != SD7_OK) return s;
+    if (c.P.onesweep && mw) {
+        uint32_t* dh = c.at<uint32_t>(S.dhist);
+        uint32_t* ctr = c.at<uint32_t>(S.dctr);
+        uint32_t* stat = c.at<uint32_t>(S.dstat);
+        const size_t sw = 256 * (size_t)mw;  // status words of one pass
+        if ((s = fill(c, c.at<uint32_t>(S.dsort), S.dsort_words, 0)) != SD7_OK) return s;
+        k_depth_hist<<<mw, 256, 0, c.st>>>(dkey, segs_all, nf, tot_all, dh);
+        LAUNCH_CHECK("k_depth_hist");
+        k_depth_pass<true, true><<<mw, 256, 0, c.st>>>(dkey, nullptr, ka, va, segs_all, nf, tot_all, 0, dh, stat,
+                                                       ctr, c.counts);
+        LAUNCH_CHECK("k_depth_pass");
+        k_depth_pass<false, true><<<mw, 256, 0, c.st>>>(ka, va, kb, order, segs_kept, nf, tot_kept, 1, dh,
+                                                        stat + sw, ctr + 1, c.counts);
+        LAUNCH_CHECK("k_depth_pass");
+        k_depth_pass<false, true><<<mw, 256, 0, c.st>>>(kb, order, ka, va, segs_kept, nf, tot_kept, 2, dh,
+                                                        stat + 2 * sw, ctr + 2, c.counts);
+        LAUNCH_CHECK("k_depth_pass");
+        k_depth_pass<false, false><<<mw, 256, 0, c.st>>>(ka, va, nullptr, order, segs_kept, nf, tot_kept, 3, dh,
+                                                         stat + 3 * sw, ctr + 3, c.counts);
+        LAUNCH_CHECK("k_depth_pass");
+    } else {
+        if ((s = radix_pass(c, true, dkey, nullptr, ka, va, segs_all, tot_all, mw, 0)) != SD7_OK) return s;
+        if ((s = radix_pass(c, false, ka, va, kb, order, segs_kept, tot_kept, mw, 8)) != SD7_OK) return s;
+        if ((s = radix_pass(c, false, kb, order, ka, va, segs_kept, tot_kept, mw, 16)) != SD7_OK) return s;
+        if ((s = radix_pass(c, false, ka, va, kb, order, segs_kept, tot_kept, mw, 24)) != SD7_OK) return s;
+    }
     if (c.P.counting) {
         // counting binner: depth-sorted boxes -> [chunk][tile] counts -> per-tile
         // prefix over chunks and tile totals -> scan of the totals (which also

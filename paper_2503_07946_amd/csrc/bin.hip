@@ -322,6 +322,241 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restric
 }
 
 // ---------------------------------------------------------------------------
+// depth sort of a small call: one launch per 8-bit digit
+//
+// For calls of few work tiles the sort's launches, not its bytes, set its
+// time.  k_depth_hist counts, per frame, the kept keys of each value of each
+// of the four digits in one read of the keys; a digit's first output slot in
+// the frame is the sum of the counts of the digits below it.  Each pass then
+// ranks its work tiles like k_radix_scatter, and a tile finds how many keys
+// of each digit the frame's earlier tiles hold by looking back over their
+// published counts (decoupled look-back): a tile publishes its own counts as
+// soon as it has them, then adds up earlier tiles' counts, newest first,
+// until it meets one that already holds the inclusive sum over all tiles
+// before it, and publishes that sum for its own successors.  Tiles take
+// their index from a counter in the order their blocks start, so a tile only
+// ever waits on tiles whose blocks are already running and publish without
+// waiting; each wait is still bounded (kLookbackSpins polls) and a wait that
+// gives up flags the frame with SD7_FLAG_SORT_STALL.  Both sorts give the
+// same order.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kStatAgg = 1u << 30;    // status word: the tile's own digit count
+constexpr uint32_t kStatIncl = 2u << 30;   // status word: inclusive count over the frame's tiles so far
+constexpr uint32_t kStatCount = (1u << 30) - 1u;
+constexpr uint32_t kLookbackSpins = 1u << 22;  // polls of an unpublished tile before a wait gives up
+constexpr int kLookWindow = 16;                 // earlier tiles a look-back step reads at once
+
+// Per frame, the kept keys of every value of every digit: dh[f][digit][256].
+__global__ __launch_bounds__(256) void k_depth_hist(const uint32_t* __restrict__ keys,
+                                                    const SortSeg* __restrict__ segs, int nseg,
+                                                    const SortTotals* __restrict__ tot, uint32_t* __restrict__ dh)
+{
+    __shared__ uint32_t h[4][256];
+    const uint32_t nwt = tot->wt;
+    for (uint32_t w = blockIdx.x; w < nwt; w += gridDim.x) {
+        const int s = seg_of_tile(segs, nseg, w);
+        const SortSeg sg = segs[s];
+        h[0][threadIdx.x] = 0; h[1][threadIdx.x] = 0; h[2][threadIdx.x] = 0; h[3][threadIdx.x] = 0;
+        __syncthreads();
+        const uint32_t begin = (w - sg.wt0) * kSortItems;
+        const uint32_t end = min(sg.len, begin + kSortItems);
+        for (uint32_t e0 = begin; e0 < end; e0 += 256) {  // uniform trip count
+            const uint32_t e = e0 + threadIdx.x;
+            const uint32_t key = e < end ? keys[sg.in_base + e] : kCulled;
+            const bool ok = key != kCulled;
+            if (ok) {
+                atomicAdd(&h[0][key & 255u], 1u);
+                atomicAdd(&h[1][(key >> 8) & 255u], 1u);
+                atomicAdd(&h[2][(key >> 16) & 255u], 1u);
+            }
+            // the top digit takes few values: one add per value and wave
+            const uint32_t top = key >> 24;
+            uint64_t act = __ballot(ok);
+            while (act) {
+                const int first = __builtin_ctzll(act);
+                const uint32_t v = __builtin_amdgcn_readlane(top, first);
+                const uint64_t peers = __ballot(ok && top == v);
+                if ((int)__lane_id() == first) atomicAdd(&h[3][v], (uint32_t)__popcll(peers));
+                act &= ~peers;
+            }
+        }
+        __syncthreads();
+        uint32_t* out = dh + (size_t)s * 1024;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const uint32_t v = h[d][threadIdx.x];
+            if (v) atomicAdd(&out[d * 256 + threadIdx.x], v);
+        }
+        __syncthreads();
+    }
+}
+
+// One pass of the small call's depth sort over digit `digit` (bits 8 * digit
+// ..).  FIRST: the keys of every Gaussian, culled ones dropped, values =
+// frame-local index; KEYS_OUT false: only the values are written (the last
+// pass).  One work tile per block; stat holds 256 status words per work tile
+// of this pass and tile_ctr the pass's tile counter, both zero at the start.
+template <bool FIRST, bool KEYS_OUT>
+__global__ __launch_bounds__(256) void k_depth_pass(const uint32_t* __restrict__ keys_in,
+                                                    const uint32_t* __restrict__ vals_in,
+                                                    uint32_t* __restrict__ keys_out,
+                                                    uint32_t* __restrict__ vals_out,
+                                                    const SortSeg* __restrict__ segs, int nseg,
+                                                    const SortTotals* __restrict__ tot, int digit,
+                                                    const uint32_t* __restrict__ dh, uint32_t* stat,
+                                                    uint32_t* tile_ctr, uint32_t* __restrict__ counts)
+{
+    __shared__ uint32_t s_goff[256];
+    __shared__ uint32_t s_wh[4][256];
+    __shared__ uint32_t s_dst[256];  // first position of each digit in the tile (digit order)
+    __shared__ uint32_t s_tmp[4], s_base[4];
+    __shared__ uint32_t s_key[kSortItems], s_val[kSortItems];
+    __shared__ uint32_t s_w;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int shift = 8 * digit;
+    if (tid == 0) s_w = atomicAdd(tile_ctr, 1u);
+    __syncthreads();
+    const uint32_t w = s_w;
+    if (w >= tot->wt) return;  // uniform over the block
+    const int s = seg_of_tile(segs, nseg, w);
+    const SortSeg sg = segs[s];
+    const uint32_t k = w - sg.wt0;
+    s_wh[0][tid] = 0; s_wh[1][tid] = 0; s_wh[2][tid] = 0; s_wh[3][tid] = 0;
+    // first output slot of digit tid in the frame: exclusive scan of the
+    // frame's digit counts
+    const uint32_t dcount = dh[(size_t)s * 1024 + digit * 256 + tid];
+    {
+        uint32_t v = dcount;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t t = __shfl_up(v, off);
+            if (lane >= off) v += t;
+        }
+        if (lane == 63) s_base[wave] = v;
+        __syncthreads();
+        uint32_t before = 0;
+#pragma unroll
+        for (int w2 = 0; w2 < 4; ++w2)
+            if (w2 < wave) before += s_base[w2];
+        s_goff[tid] = sg.out_base + before + v - dcount;
+    }
+    const uint64_t lt = lanemask_lt();
+    const uint32_t wbase = k * kSortItems + wave * (kSortPerThread * 64);
+    uint32_t key[kSortPerThread], val[kSortPerThread], rank[kSortPerThread];
+    uint32_t okmask = 0;
+#pragma unroll
+    for (int r = 0; r < kSortPerThread; ++r) {
+        const uint32_t e = wbase + r * 64 + lane;
+        bool ok = e < sg.len;
+        const uint32_t kk = ok ? keys_in[sg.in_base + e] : 0u;
+        if (FIRST) ok = ok && kk != kCulled;
+        const uint32_t vv = FIRST ? e : (ok ? vals_in[sg.in_base + e] : 0u);
+        const uint32_t d = (kk >> shift) & 255u;
+        uint64_t peers = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        const uint32_t below = __popcll(peers & lt);
+        uint32_t prev = 0;
+        if (ok) prev = s_wh[wave][d];
+        if (ok && below == 0) s_wh[wave][d] = prev + __popcll(peers);
+        key[r] = kk;
+        val[r] = vv;
+        rank[r] = prev + below;
+        okmask |= (ok ? 1u : 0u) << r;
+    }
+    __syncthreads();
+    uint32_t run = 0;  // the tile's count of digit tid
+#pragma unroll
+    for (int w2 = 0; w2 < 4; ++w2) {
+        const uint32_t t = s_wh[w2][tid];
+        s_wh[w2][tid] = run;
+        run += t;
+    }
+    // publish the tile's count of digit tid, then look back
+    uint32_t* const my = stat + (size_t)w * 256 + tid;
+    __hip_atomic_store(my, (k == 0 ? kStatIncl : kStatAgg) | run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t excl = 0;
+    if (k > 0) {
+        // examine the earlier tiles kLookWindow at a time (independent loads),
+        // newest first, up to the first one that has not published yet
+        bool stalled = false;
+        uint32_t j = w, polls = 0;  // tiles below j are still to be added
+        for (;;) {
+            uint32_t v[kLookWindow];
+#pragma unroll
+            for (int q = 0; q < kLookWindow; ++q) {
+                const uint32_t jj = j - 1u - (uint32_t)q;
+                // before the frame's first tile: an inclusive count of zero
+                v[q] = (jj >= sg.wt0 && jj < j)
+                           ? __hip_atomic_load(stat + (size_t)jj * 256 + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                           : kStatIncl;
+            }
+            uint32_t used = 0;
+            bool done = false;
+#pragma unroll
+            for (int q = 0; q < kLookWindow; ++q) {
+                if (!done && used == (uint32_t)q && (v[q] & (kStatAgg | kStatIncl))) {
+                    excl += v[q] & kStatCount;
+                    used = q + 1;
+                    done = (v[q] & kStatIncl) != 0;
+                }
+            }
+            if (done) break;
+            j -= used;
+            if (used == 0) {
+                if (++polls > kLookbackSpins) {
+                    stalled = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __hip_atomic_store(my, kStatIncl | (excl + run), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (stalled) atomicOr(&counts[s * SD7_CNT_WORDS + SD7_CNT_FLAGS], SD7_FLAG_SORT_STALL);
+    }
+    s_goff[tid] += excl;
+    // exclusive scan of the tile's digit counts over the 256 digits
+    {
+        uint32_t v = run;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t t = __shfl_up(v, off);
+            if (lane >= off) v += t;
+        }
+        if (lane == 63) s_tmp[wave] = v;
+        __syncthreads();
+        uint32_t before = 0;
+#pragma unroll
+        for (int w2 = 0; w2 < 4; ++w2)
+            if (w2 < wave) before += s_tmp[w2];
+        s_dst[tid] = before + v - run;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortPerThread; ++r) {
+        if ((okmask >> r) & 1u) {
+            const uint32_t d = (key[r] >> shift) & 255u;
+            const uint32_t q = s_dst[d] + s_wh[wave][d] + rank[r];
+            s_key[q] = key[r];
+            s_val[q] = val[r];
+        }
+    }
+    __syncthreads();
+    const uint32_t ntile = s_tmp[0] + s_tmp[1] + s_tmp[2] + s_tmp[3];  // elements the tile keeps
+    for (uint32_t q = tid; q < ntile; q += 256) {
+        const uint32_t kk = s_key[q];
+        const uint32_t d = (kk >> shift) & 255u;
+        const uint32_t p = s_goff[d] + (q - s_dst[d]);
+        if (KEYS_OUT) keys_out[p] = kk;
+        vals_out[p] = s_val[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // set-up, gather, emit, ranges
 // ---------------------------------------------------------------------------
 __global__ void k_fill_u32(uint32_t* __restrict__ p, size_t count, uint32_t value)

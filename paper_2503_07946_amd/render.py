@@ -272,6 +272,8 @@ class Renderer:
             self.stage(s, b, stream)
         if exact:
             c = self.read_counts(b, stream)
+            if np.any(c[:, L.SD7_CNT_FLAGS] & L.SD7_FLAG_SORT_STALL):
+                raise L.Sd7Error(L.SD7_EHIP, "depth sort stalled (SD7_FLAG_SORT_STALL)")
             if np.any(c[:, L.SD7_CNT_FLAGS] & L.SD7_FLAG_PAIR_OVERFLOW):
                 need = int(sum(-(-int(x) // L.SD7_PAIR_ROUND) * L.SD7_PAIR_ROUND for x in c[:, L.SD7_CNT_NEEDED]))
                 b2 = self.batch(frames, need)

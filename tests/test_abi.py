@@ -44,7 +44,7 @@ def test_constants_match_the_header():
     defines = dict(re.findall(r"#define (SD7_[A-Z_]+) \(?(-?\d+)u?\)?", open(HEADER).read()))
     for name in ("SD7_MAX_FRAMES", "SD7_TILE", "SD7_PAIR_ROUND", "SD7_CNT_KEPT", "SD7_CNT_PAIRS",
                  "SD7_CNT_PAIR_BASE", "SD7_CNT_FLAGS", "SD7_CNT_NEEDED", "SD7_CNT_WORDS", "SD7_AGR_WEIGHTS",
-                 "SD7_OUT_SLICED", "SD7_FLAG_PAIR_OVERFLOW"):
+                 "SD7_OUT_SLICED", "SD7_FLAG_PAIR_OVERFLOW", "SD7_FLAG_SORT_STALL"):
         assert int(defines[name]) == getattr(L, name), name
     assert serve.PAIR_ROUND == L.SD7_PAIR_ROUND
 
