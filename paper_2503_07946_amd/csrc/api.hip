@@ -96,13 +96,15 @@ struct Plan {
     BlockMap kmap;   // one block per (frame, chunk)
     uint32_t kblocks;
     BlockMap rmap;   // blocks of 256 tiles per frame
-    uint32_t cblocks, rblocks;
+    BlockMap qmap;   // blocks of 64 tiles per frame
+    uint32_t cblocks, rblocks, qblocks;
     size_t matrix_entries;
     size_t cnt;      // workspace offset of the count matrix
     size_t ttot;     // workspace offset of the per-tile totals (then their scan)
 };
 
-constexpr uint32_t kOneSweepTiles = 512;  // depth-sort work tiles up to which a call sorts one launch per digit
+constexpr uint32_t kOneSweepTiles = 512;
+constexpr uint32_t kScanSplitTiles = 16384;  // tiles of a call up to which the column scan splits its chunks  // depth-sort work tiles up to which a call sorts one launch per digit
 constexpr uint64_t kBinWaves = 131072; // (chunk, group) waves the counting binner aims for per call
 constexpr uint64_t kMaxChunks = 512;   // chunks per frame (the depth of the per-tile column scan)
 constexpr size_t kMaxMatrix = (size_t)1 << 28;  // count-matrix entries of one call
@@ -164,9 +166,11 @@ sd7_status make_plan(const sd7_frame* fr, int nf, int64_t cap, Plan& P, bool nee
         P.cmap.start[f] = P.cblocks;
         P.kmap.start[f] = P.kblocks;
         P.rmap.start[f] = P.rblocks;
+        P.qmap.start[f] = P.qblocks;
         P.kblocks += P.nch[f];
         P.cblocks += P.nch[f] * groups;
         P.rblocks += ceil_div(tx * ty, 256);
+        P.qblocks += ceil_div(tx * ty, 64);
         P.matrix_entries += (size_t)P.nch[f] * tx * ty;
     }
     P.gmap.start[nf] = P.gblocks;
@@ -209,7 +213,8 @@ sd7_status make_plan(const sd7_frame* fr, int nf, int64_t cap, Plan& P, bool nee
     P.cmap.start[nf] = P.cblocks;
     P.kmap.start[nf] = P.kblocks;
     P.rmap.start[nf] = P.rblocks;
-    P.cmap.nf = P.kmap.nf = P.rmap.nf = nf;
+    P.qmap.start[nf] = P.qblocks;
+    P.cmap.nf = P.kmap.nf = P.rmap.nf = P.qmap.nf = nf;
     P.max_tiles = max_tiles;
     P.counting = max_tiles <= kMaxCountTiles && P.matrix_entries <= kMaxMatrix;
     if (ntot >= (int64_t)1 << 31) return fail(SD7_EINVAL, "total Gaussians %lld >= 2^31", (long long)ntot);
@@ -633,7 +638,12 @@ sd7_status do_bin(const Call& c)
                                                                                       srect, cnt);
             LAUNCH_CHECK("k_tile_count");
         }
-        k_tile_colscan<<<c.P.rblocks, 256, 0, c.st>>>(c.tab, c.P.rmap, cnt, ttot);
+        {
+            // several runs of chunks per tile where the call has too few
+            // tiles to fill the chip with one lane each
+            const uint32_t ns = c.P.tblocks <= kScanSplitTiles ? kScanSlices : 1;
+            k_tile_colscan<<<c.P.qblocks, 64 * ns, 0, c.st>>>(c.tab, c.P.qmap, ns, cnt, ttot);
+        }
         LAUNCH_CHECK("k_tile_colscan");
         if ((s = fill(c, words, 1, 0)) != SD7_OK) return s;
         if ((s = scan(c, ttot, ttiles, nullptr, ttiles, words)) != SD7_OK) return s;

@@ -915,9 +915,6 @@ constexpr uint32_t kFlushAhead = 2;  // flush stores whose stage reads are issue
 // (lgkmcnt 0; vmcnt and expcnt at their maxima).
 constexpr int kWaitLgkm0 = 0xC07F;
 
-// Third word of a raw buffer resource on gfx9-class GPUs (32-bit data format,
-// no swizzle): range-checked loads at byte offsets below the record count.
-constexpr int kBufferWord3 = 0x00020000;
 
 // One block (256 lanes) per (frame, chunk) writes the chunk's row of the
 // count matrix.  Per-row difference array over the frame's tiles in LDS: a
@@ -1155,19 +1152,49 @@ __global__ __launch_bounds__(64) void k_group_place(const FrameDev* __restrict__
 }
 
 // Per tile, exclusive prefix over the chunks (in place) and the tile's total.
-// One lane per (frame, tile); rows are read coalesced, eight at a time.
-__global__ __launch_bounds__(256) void k_tile_colscan(const FrameDev* __restrict__ tab, BlockMap tm,
-                                                      uint32_t* __restrict__ cnt, uint32_t* __restrict__ ttot)
+// A block holds 64 tiles of one frame and ns waves (1 <= ns <= kScanSlices);
+// wave s takes the s-th run of consecutive chunks, so each lane walks
+// nch / ns rows instead of all nch.  With several runs each wave first sums
+// its run, the runs' sums of one tile are prefixed through LDS, and each wave
+// then rewrites its run as exclusive prefixes from its start; one run is
+// rewritten in a single pass.  Rows are read coalesced (64 tiles of one chunk
+// per wave load), eight at a time.
+constexpr uint32_t kScanSlices = 8;
+
+__global__ __launch_bounds__(64 * kScanSlices) void k_tile_colscan(const FrameDev* __restrict__ tab, BlockMap qm,
+                                                                   uint32_t ns, uint32_t* __restrict__ cnt,
+                                                                   uint32_t* __restrict__ ttot)
 {
-    const int f = frame_of_block(tm, blockIdx.x);
+    __shared__ uint32_t s_sum[kScanSlices][64];
+    const int f = frame_of_block(qm, blockIdx.x);
     const FrameDev& F = tab[f];
-    const uint32_t t = (blockIdx.x - tm.start[f]) * 256 + threadIdx.x;
+    const uint32_t lane = threadIdx.x & 63, sl = threadIdx.x >> 6;
+    const uint32_t t = (blockIdx.x - qm.start[f]) * 64 + lane;
     const uint32_t T = F.tiles_x * F.tiles_y;
-    if (t >= T) return;
+    const uint32_t nch = F.nch, per = (nch + ns - 1) / ns;
+    const uint32_t c0 = min(nch, sl * per), c1 = min(nch, c0 + per);
     uint32_t* p = cnt + F.m0 + t;
-    const uint32_t nch = F.nch;
-    uint32_t run = 0, c = 0;
-    for (; c + 8 <= nch; c += 8) {
+    uint32_t run = 0;
+    if (ns > 1) {  // uniform over the block
+        uint32_t sum = 0;
+        if (t < T) {
+            uint32_t c = c0;
+            for (; c + 8 <= c1; c += 8) {
+                uint32_t v[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) v[k] = p[(size_t)(c + k) * T];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) sum += v[k];
+            }
+            for (; c < c1; ++c) sum += p[(size_t)c * T];
+        }
+        s_sum[sl][lane] = sum;
+        __syncthreads();
+        for (uint32_t q = 0; q < sl; ++q) run += s_sum[q][lane];
+    }
+    if (t >= T) return;
+    uint32_t c = c0;
+    for (; c + 8 <= c1; c += 8) {
         uint32_t v[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) v[k] = p[(size_t)(c + k) * T];
@@ -1177,12 +1204,12 @@ __global__ __launch_bounds__(256) void k_tile_colscan(const FrameDev* __restrict
             run += v[k];
         }
     }
-    for (; c < nch; ++c) {
+    for (; c < c1; ++c) {
         const uint32_t v = p[(size_t)c * T];
         p[(size_t)c * T] = run;
         run += v;
     }
-    ttot[F.t0 + t] = run;
+    if (sl == ns - 1) ttot[F.t0 + t] = run;
 }
 
 // Tile ranges from the scanned tile totals: tile t of frame f starts after

@@ -69,6 +69,9 @@ struct FrameDev {
     float limx, limy;  // view-ray ratio clamps of J: 1.3 x (W/2) / fx, 1.3 x (H/2) / fy
 };
 
+// Third word of a raw buffer resource on gfx9-class GPUs (32-bit data format,
+// no swizzle): range-checked loads at byte offsets below the record count.
+constexpr int kBufferWord3 = 0x00020000;
 constexpr uint32_t kMaxCountTiles = 32768;  // tiles per frame the counting binner takes (more: radix binner)
 constexpr uint32_t kGroup = 8;              // tiles per side of a counting-binner group (one lane per tile)
 
