@@ -6,10 +6,11 @@
 // offset dx and its products are shared by the lane's four pixels, and band
 // k is pixel k of every lane.  The wave walks the tile's list in order; a
 // splat record is the same for every lane, so it is read with scalar loads
-// through the scalar cache into SGPRs (no LDS staging, no barriers), one
-// splat ahead of the one being blended, and the vector ALUs take it as scalar
-// operands.  A band none of whose 64 pixels the splat reaches skips the
-// blend; the wave leaves the list as soon as all 256 pixels have stopped.
+// through the scalar cache into SGPRs (no LDS staging, no barriers), a batch
+// of two records ahead of the pair being blended, and the vector ALUs take
+// it as scalar operands.  A band none of whose 64 pixels the splat reaches
+// skips the blend; the wave leaves the list as soon as all 256 pixels have
+// stopped.
 //
 // Per (pixel, splat), with the record's exponent coefficients
 // (A, B, C) = -(a, 2b, c) log2(e) / 2 and lo = log2(alpha_c):
@@ -62,6 +63,9 @@ __device__ __forceinline__ void splat_exponents(const Splat& s, float fx, float 
     D = fmaf(s.C16, 2.0f, D);
     p[3] = p[2] + D;
 }
+
+// List entries whose records one scalar-load batch brings in.
+constexpr uint32_t kRasterBatch = 2;
 
 template <bool COUNT>
 __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab, BlockMap bm,
@@ -125,34 +129,48 @@ __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab,
             }
         }
     };
-    // Two splat records in scalar registers, even and odd entries: while one
-    // is blended the other is being loaded.  Scalar loads complete out of
-    // order and are waited for all at once, so each load is issued right
-    // after the wait for the record the next blend uses; past the list's end
-    // the loads repeat its last entry (in bounds, unused); indices are
-    // clamped where used.
+    // Splat records in scalar registers, two batches of kRasterBatch entries
+    // (a, b): while one batch is blended the next is being loaded.  Scalar
+    // loads complete out of order and are waited for all at once, so a
+    // batch's loads are issued right after the wait for the batch the next
+    // blends use; past the list's end the loads repeat its last entry (in
+    // bounds, unused); indices are clamped where used.
     const uint32_t eend = rg.y - 1;
-    Splat s0{}, s1{};
-    uint32_t gi = 0;  // index of the next entry to load
     if (rg.x < rg.y) {
-        s0 = load_splat(rec, min(pair_g[rg.x], gmax));
-        gi = pair_g[min(rg.x + 1, eend)];
-    }
-    for (uint32_t e = rg.x; e < rg.y; e += 2) {
-        if (((e - rg.x) & 7) == 0 &&
-            __ballot(fminf(fminf(th[0], th[1]), fminf(th[2], th[3])) < kFar) == 0)
-            break;
-        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): s0 and gi are in
-        s1 = load_splat(rec, min(gi, gmax));         // entry e + 1
-        uint32_t gn = pair_g[min(e + 2, eend)];
-        asm volatile("" ::: "memory");  // keep the loads ahead of the blend
-        blend(s0, e);
-        if (e + 1 >= rg.y) break;
-        __builtin_amdgcn_s_waitcnt(0xC07F);  // s1 and gn are in
-        s0 = load_splat(rec, min(gn, gmax));         // entry e + 2
-        gi = pair_g[min(e + 3, eend)];
-        asm volatile("" ::: "memory");
-        blend(s1, e + 1);
+        constexpr uint32_t NB = kRasterBatch;
+        Splat a[NB], b[NB];
+        uint32_t ia[NB], ib[NB];  // list indices of the batch after the next
+#pragma unroll
+        for (uint32_t j = 0; j < NB; ++j) ia[j] = pair_g[min(rg.x + j, eend)];
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+#pragma unroll
+        for (uint32_t j = 0; j < NB; ++j) a[j] = load_splat(rec, min(ia[j], gmax));
+#pragma unroll
+        for (uint32_t j = 0; j < NB; ++j) ib[j] = pair_g[min(rg.x + NB + j, eend)];
+        for (uint32_t e = rg.x; e < rg.y; e += 2 * NB) {
+            if (((e - rg.x) & 7) == 0 &&
+                __ballot(fminf(fminf(th[0], th[1]), fminf(th[2], th[3])) < kFar) == 0)
+                break;
+            __builtin_amdgcn_s_waitcnt(0xC07F);  // batch a and indices ib are in
+#pragma unroll
+            for (uint32_t j = 0; j < NB; ++j) b[j] = load_splat(rec, min(ib[j], gmax));
+#pragma unroll
+            for (uint32_t j = 0; j < NB; ++j) ia[j] = pair_g[min(e + 2 * NB + j, eend)];
+            asm volatile("" ::: "memory");  // keep the loads ahead of the blends
+#pragma unroll
+            for (uint32_t j = 0; j < NB; ++j)
+                if (e + j < rg.y) blend(a[j], e + j);
+            if (e + NB >= rg.y) break;
+            __builtin_amdgcn_s_waitcnt(0xC07F);  // batch b and indices ia are in
+#pragma unroll
+            for (uint32_t j = 0; j < NB; ++j) a[j] = load_splat(rec, min(ia[j], gmax));
+#pragma unroll
+            for (uint32_t j = 0; j < NB; ++j) ib[j] = pair_g[min(e + 3 * NB + j, eend)];
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (uint32_t j = 0; j < NB; ++j)
+                if (e + NB + j < rg.y) blend(b[j], e + NB + j);
+        }
     }
     const size_t plane = (size_t)F.W * F.H;
 #pragma unroll
