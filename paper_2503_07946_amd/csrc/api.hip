@@ -91,6 +91,7 @@ struct Plan {
     bool counting;
     bool onesweep;  // depth sort with one launch per digit (calls of few work tiles)
     uint32_t max_tiles;
+    int64_t max_n;  // Gaussians of the largest frame
     uint32_t nch[SD7_MAX_FRAMES], m0[SD7_MAX_FRAMES];
     BlockMap cmap;   // one block (wave) per (frame, chunk, tile group)
     BlockMap kmap;   // one block per (frame, chunk)
@@ -159,6 +160,7 @@ sd7_status make_plan(const sd7_frame* fr, int nf, int64_t cap, Plan& P, bool nee
         ntot += n;
         ttot += (int64_t)tx * ty;
         max_tiles = std::max(max_tiles, tx * ty);
+        P.max_n = std::max(P.max_n, n);
         wt_depth += ceil_div(n, kSortItems);
         const uint32_t groups = ceil_div(tx, kGroup) * ceil_div(ty, kGroup);
         P.nch[f] = chunk_count(n, groups, nf);
@@ -702,12 +704,19 @@ sd7_status do_bin(const Call& c)
 sd7_status do_raster(const Call& c)
 {
     const sd7_layout& L = c.P.L;
-    if (c.count)
-        k_raster<true><<<c.P.tblocks, 64, 0, c.st>>>(c.tab, c.P.tmap, c.at<uint2>(L.off_ranges),
-                                                     c.at<uint32_t>(L.off_pair_g), c.at<float4>(L.off_splat));
+    const uint2* rg = c.at<uint2>(L.off_ranges);
+    const uint32_t* pg = c.at<uint32_t>(L.off_pair_g);
+    const float4* sp = c.at<float4>(L.off_splat);
+    // 64-bit addressing where a frame's splat records span 4 GiB or more
+    const bool wide = c.P.max_n > (int64_t)(UINT32_MAX / (4 * kSplatFloats));
+    if (c.count && wide)
+        k_raster<true, true><<<c.P.tblocks, 64, 0, c.st>>>(c.tab, c.P.tmap, rg, pg, sp);
+    else if (c.count)
+        k_raster<true, false><<<c.P.tblocks, 64, 0, c.st>>>(c.tab, c.P.tmap, rg, pg, sp);
+    else if (wide)
+        k_raster<false, true><<<c.P.tblocks, 64, 0, c.st>>>(c.tab, c.P.tmap, rg, pg, sp);
     else
-        k_raster<false><<<c.P.tblocks, 64, 0, c.st>>>(c.tab, c.P.tmap, c.at<uint2>(L.off_ranges),
-                                                      c.at<uint32_t>(L.off_pair_g), c.at<float4>(L.off_splat));
+        k_raster<false, false><<<c.P.tblocks, 64, 0, c.st>>>(c.tab, c.P.tmap, rg, pg, sp);
     LAUNCH_CHECK("k_raster");
     return SD7_OK;
 }

@@ -67,7 +67,7 @@ __device__ __forceinline__ void splat_exponents(const Splat& s, float fx, float 
 // List entries whose records one scalar-load batch brings in.
 constexpr uint32_t kRasterBatch = 2;
 
-template <bool COUNT>
+template <bool COUNT, bool WIDE>
 __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab, BlockMap bm,
                                                const uint2* __restrict__ ranges,
                                                const uint32_t* __restrict__ pair_g,
@@ -135,41 +135,55 @@ __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab,
     // batch's loads are issued right after the wait for the batch the next
     // blends use; past the list's end the loads repeat its last entry (in
     // bounds, unused); indices are clamped where used.
-    const uint32_t eend = rg.y - 1;
     if (rg.x < rg.y) {
         constexpr uint32_t NB = kRasterBatch;
+        // Entry rg.x + r of the list (r clamped to the list) and the record
+        // of Gaussian g (clamped to the frame).  Unless WIDE, both are read
+        // at 32-bit byte offsets from the list's start and the frame's first
+        // record, which the scalar loads take as an offset register (the
+        // caller sets WIDE where the frame's records span 4 GiB or more).
+        const uint32_t lmax = rg.y - 1 - rg.x;
+        auto idx = [&](uint32_t r) {
+            if constexpr (WIDE) return pair_g[rg.x + min(r, lmax)];
+            return *(const uint32_t*)((const char*)(pair_g + rg.x) + 4u * min(r, lmax));
+        };
+        auto rec_at = [&](uint32_t g) {
+            if constexpr (WIDE) return load_splat(rec, min(g, gmax));
+            const float4* q = (const float4*)((const char*)rec + 48u * min(g, gmax));
+            const float4 p0 = q[0], p1 = q[1], p2 = q[2];
+            return Splat{p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x, p2.y};
+        };
         Splat a[NB], b[NB];
         uint32_t ia[NB], ib[NB];  // list indices of the batch after the next
 #pragma unroll
-        for (uint32_t j = 0; j < NB; ++j) ia[j] = pair_g[min(rg.x + j, eend)];
+        for (uint32_t j = 0; j < NB; ++j) ia[j] = idx(j);
         __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
 #pragma unroll
-        for (uint32_t j = 0; j < NB; ++j) a[j] = load_splat(rec, min(ia[j], gmax));
+        for (uint32_t j = 0; j < NB; ++j) a[j] = rec_at(ia[j]);
 #pragma unroll
-        for (uint32_t j = 0; j < NB; ++j) ib[j] = pair_g[min(rg.x + NB + j, eend)];
-        for (uint32_t e = rg.x; e < rg.y; e += 2 * NB) {
-            if (((e - rg.x) & 7) == 0 &&
-                __ballot(fminf(fminf(th[0], th[1]), fminf(th[2], th[3])) < kFar) == 0)
+        for (uint32_t j = 0; j < NB; ++j) ib[j] = idx(NB + j);
+        for (uint32_t r = 0; r <= lmax; r += 2 * NB) {
+            if ((r & 7) == 0 && __ballot(fminf(fminf(th[0], th[1]), fminf(th[2], th[3])) < kFar) == 0)
                 break;
             __builtin_amdgcn_s_waitcnt(0xC07F);  // batch a and indices ib are in
 #pragma unroll
-            for (uint32_t j = 0; j < NB; ++j) b[j] = load_splat(rec, min(ib[j], gmax));
+            for (uint32_t j = 0; j < NB; ++j) b[j] = rec_at(ib[j]);
 #pragma unroll
-            for (uint32_t j = 0; j < NB; ++j) ia[j] = pair_g[min(e + 2 * NB + j, eend)];
+            for (uint32_t j = 0; j < NB; ++j) ia[j] = idx(r + 2 * NB + j);
             asm volatile("" ::: "memory");  // keep the loads ahead of the blends
 #pragma unroll
             for (uint32_t j = 0; j < NB; ++j)
-                if (e + j < rg.y) blend(a[j], e + j);
-            if (e + NB >= rg.y) break;
+                if (r + j <= lmax) blend(a[j], rg.x + r + j);
+            if (r + NB > lmax) break;
             __builtin_amdgcn_s_waitcnt(0xC07F);  // batch b and indices ia are in
 #pragma unroll
-            for (uint32_t j = 0; j < NB; ++j) a[j] = load_splat(rec, min(ia[j], gmax));
+            for (uint32_t j = 0; j < NB; ++j) a[j] = rec_at(ia[j]);
 #pragma unroll
-            for (uint32_t j = 0; j < NB; ++j) ib[j] = pair_g[min(e + 3 * NB + j, eend)];
+            for (uint32_t j = 0; j < NB; ++j) ib[j] = idx(r + 3 * NB + j);
             asm volatile("" ::: "memory");
 #pragma unroll
             for (uint32_t j = 0; j < NB; ++j)
-                if (e + NB + j < rg.y) blend(b[j], e + NB + j);
+                if (r + NB + j <= lmax) blend(b[j], rg.x + r + NB + j);
         }
     }
     const size_t plane = (size_t)F.W * F.H;
