@@ -24,6 +24,8 @@
 // same explicit fused operations, so they take the same decisions.
 #include "common.h"
 
+#include <type_traits>
+
 namespace sd7 {
 
 constexpr float kLog2AlphaMin = -7.99435343685886f;  // log2(1/255)
@@ -154,7 +156,28 @@ __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab,
             return Splat{p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w, p2.x, p2.y};
         };
         Splat a[NB], b[NB];
-        uint32_t ia[NB], ib[NB];  // list indices of the batch after the next
+        uint32_t ia[NB], ib[NB];  // list indices of a batch to come
+        // One half step: wait for the batch `cur` (entries r ..) and the
+        // indices `inxt` of the batch after it, start loading that batch
+        // (`nxt`) and the indices `ifree` of the one after, then blend `cur`
+        // (entry by entry up to the list's end when GUARD).
+        auto half = [&](auto guard, Splat (&cur)[NB], Splat (&nxt)[NB], const uint32_t (&inxt)[NB],
+                        uint32_t (&ifree)[NB], uint32_t r) {
+            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+#pragma unroll
+            for (uint32_t j = 0; j < NB; ++j) nxt[j] = rec_at(inxt[j]);
+#pragma unroll
+            for (uint32_t j = 0; j < NB; ++j) ifree[j] = idx(r + 2 * NB + j);
+            asm volatile("" ::: "memory");  // keep the loads ahead of the blends
+#pragma unroll
+            for (uint32_t j = 0; j < NB; ++j)
+                if (!decltype(guard)::value || r + j <= lmax) blend(cur[j], rg.x + r + j);
+        };
+        using Full = std::false_type;
+        using Guarded = std::true_type;
+        auto all_stopped = [&]() {
+            return __ballot(fminf(fminf(th[0], th[1]), fminf(th[2], th[3])) < kFar) == 0;
+        };
 #pragma unroll
         for (uint32_t j = 0; j < NB; ++j) ia[j] = idx(j);
         __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
@@ -162,28 +185,21 @@ __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab,
         for (uint32_t j = 0; j < NB; ++j) a[j] = rec_at(ia[j]);
 #pragma unroll
         for (uint32_t j = 0; j < NB; ++j) ib[j] = idx(NB + j);
-        for (uint32_t r = 0; r <= lmax; r += 2 * NB) {
-            if ((r & 7) == 0 && __ballot(fminf(fminf(th[0], th[1]), fminf(th[2], th[3])) < kFar) == 0)
-                break;
-            __builtin_amdgcn_s_waitcnt(0xC07F);  // batch a and indices ib are in
-#pragma unroll
-            for (uint32_t j = 0; j < NB; ++j) b[j] = rec_at(ib[j]);
-#pragma unroll
-            for (uint32_t j = 0; j < NB; ++j) ia[j] = idx(r + 2 * NB + j);
-            asm volatile("" ::: "memory");  // keep the loads ahead of the blends
-#pragma unroll
-            for (uint32_t j = 0; j < NB; ++j)
-                if (r + j <= lmax) blend(a[j], rg.x + r + j);
+        // whole groups of 4 NB entries, then the rest with guards; the wave
+        // checks every 4 NB entries whether all its pixels have stopped
+        uint32_t r = 0;
+        for (; r + 4 * NB <= lmax + 1; r += 4 * NB) {
+            if (all_stopped()) break;
+            half(Full{}, a, b, ib, ia, r);
+            half(Full{}, b, a, ia, ib, r + NB);
+            half(Full{}, a, b, ib, ia, r + 2 * NB);
+            half(Full{}, b, a, ia, ib, r + 3 * NB);
+        }
+        for (; r <= lmax; r += 2 * NB) {
+            if (all_stopped()) break;
+            half(Guarded{}, a, b, ib, ia, r);
             if (r + NB > lmax) break;
-            __builtin_amdgcn_s_waitcnt(0xC07F);  // batch b and indices ia are in
-#pragma unroll
-            for (uint32_t j = 0; j < NB; ++j) a[j] = rec_at(ia[j]);
-#pragma unroll
-            for (uint32_t j = 0; j < NB; ++j) ib[j] = idx(r + 3 * NB + j);
-            asm volatile("" ::: "memory");
-#pragma unroll
-            for (uint32_t j = 0; j < NB; ++j)
-                if (r + NB + j <= lmax) blend(b[j], rg.x + r + NB + j);
+            half(Guarded{}, b, a, ia, ib, r + NB);
         }
     }
     const size_t plane = (size_t)F.W * F.H;
