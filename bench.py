@@ -47,8 +47,8 @@ FP32_NONPACKED_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 RASTER_OPS_PER_TEST = 12
 RASTER_OPS_PER_CONTRIBUTION = 12
 RASTER_SRC_DIR = "paper_2503_07946_amd/csrc"
-RASTER_SRC_SHA256 = "828ed9ff5f2c13ae35c7b8c612429177a909e7b65d616494a2633e2bbbf7d380"
-RASTER_TRAFFIC_BYTES = 2344450048       # (988501 KiB x 2 + 312500 KiB) x 1024
+RASTER_SRC_SHA256 = "2eafbc40d8e031923347e1555ce12c084ea65a8df077a9e89f1076d68eeaf6d0"
+RASTER_TRAFFIC_BYTES = 2386223104       # (1008898 KiB x 2 + 312500 KiB) x 1024
 RASTER_VALU_INSTRUCTIONS = 1108255342   # SQ_INSTS_VALU per launch (wave64 instructions)
 
 
