@@ -47,9 +47,9 @@ FP32_NONPACKED_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 RASTER_OPS_PER_TEST = 12
 RASTER_OPS_PER_CONTRIBUTION = 12
 RASTER_SRC_DIR = "paper_2503_07946_amd/csrc"
-RASTER_SRC_SHA256 = "2eafbc40d8e031923347e1555ce12c084ea65a8df077a9e89f1076d68eeaf6d0"
-RASTER_TRAFFIC_BYTES = 2386223104       # (1008898 KiB x 2 + 312500 KiB) x 1024
-RASTER_VALU_INSTRUCTIONS = 1108255342   # SQ_INSTS_VALU per launch (wave64 instructions)
+RASTER_SRC_SHA256 = "8186d670ba0e1d3fe6bd5f30342a62681aea63c89381758ba9f7cc2a80779d45"
+RASTER_TRAFFIC_BYTES = 2388686848       # (1010101 KiB x 2 + 312500 KiB) x 1024
+RASTER_VALU_INSTRUCTIONS = 1108568418   # SQ_INSTS_VALU per launch (wave64 instructions)
 
 
 def raster_src_digest() -> str:
