@@ -647,19 +647,31 @@ sd7_status do_bin(const Call& c)
             k_tile_colscan<<<c.P.qblocks, 64 * ns, 0, c.st>>>(c.tab, c.P.qmap, ns, cnt, ttot);
         }
         LAUNCH_CHECK("k_tile_colscan");
-        if ((s = fill(c, words, 1, 0)) != SD7_OK) return s;
-        if ((s = scan(c, ttot, ttiles, nullptr, ttiles, words)) != SD7_OK) return s;
-        k_setup_pairs<<<1, 64, 0, c.st>>>(c.tab, nf, ttiles, true, ttot, words, (uint32_t)L.pair_capacity,
-                                          c.counts, segs_pairs, tot_pairs);
-        LAUNCH_CHECK("k_setup_pairs");
+        // scan of the tile totals, arena, ranges: one block for calls of few
+        // tiles (the ranges need only the scan and the arena)
+        const bool one_block = ttiles <= kFinishTiles;
+        if (one_block) {
+            k_tiles_finish<<<1, kFinishThreads, 0, c.st>>>(c.tab, nf, ttiles, (uint32_t)L.pair_capacity, ttot,
+                                                          c.counts, segs_pairs, tot_pairs,
+                                                          c.at<uint2>(L.off_ranges));
+            LAUNCH_CHECK("k_tiles_finish");
+        } else {
+            if ((s = fill(c, words, 1, 0)) != SD7_OK) return s;
+            if ((s = scan(c, ttot, ttiles, nullptr, ttiles, words)) != SD7_OK) return s;
+            k_setup_pairs<<<1, 64, 0, c.st>>>(c.tab, nf, ttiles, true, ttot, words, (uint32_t)L.pair_capacity,
+                                              c.counts, segs_pairs, tot_pairs);
+            LAUNCH_CHECK("k_setup_pairs");
+        }
         if (c.P.cblocks) {
             k_group_place<<<c.P.cblocks, 64, 0, c.st>>>(c.tab, c.P.cmap, c.counts, order, srect,
                                                          c.at<uint32_t>(S.sspan), cnt, ttot,
                                                          c.at<uint32_t>(L.off_pair_g));
             LAUNCH_CHECK("k_group_place");
         }
-        k_tile_ranges<<<c.P.rblocks, 256, 0, c.st>>>(c.tab, c.P.rmap, c.counts, ttot, c.at<uint2>(L.off_ranges));
-        LAUNCH_CHECK("k_tile_ranges");
+        if (!one_block) {
+            k_tile_ranges<<<c.P.rblocks, 256, 0, c.st>>>(c.tab, c.P.rmap, c.counts, ttot, c.at<uint2>(L.off_ranges));
+            LAUNCH_CHECK("k_tile_ranges");
+        }
         return SD7_OK;
     }
     // tiles per sorted Gaussian -> exclusive offsets

@@ -705,15 +705,15 @@ __global__ __launch_bounds__(kBlock) void k_gather_boxes(const FrameDev* __restr
 // are read in parallel; the arena is then handed out in frame order (a frame
 // that does not fit gets none, and later frames may still fit), a walk over
 // values already in registers.
-__global__ __launch_bounds__(64) void k_setup_pairs(const FrameDev* __restrict__ tab, int nf, uint32_t len_total,
-                                                    bool by_tiles, const uint32_t* __restrict__ toff,
-                                                    const uint32_t* __restrict__ toff_total, uint32_t capacity,
-                                                    uint32_t* __restrict__ counts, SortSeg* __restrict__ segs,
-                                                    SortTotals* __restrict__ tot)
+// The work of one wave (lane = threadIdx.x % 64 < 64 frames); returns the
+// lane's frame's pair count and first arena slot (0 for lanes past nf).
+__device__ __forceinline__ uint2 setup_pairs_wave(const FrameDev* __restrict__ tab, int nf, uint32_t len_total,
+                                                  bool by_tiles, const uint32_t* __restrict__ toff,
+                                                  uint32_t total, uint32_t capacity,
+                                                  uint32_t* __restrict__ counts, SortSeg* __restrict__ segs,
+                                                  SortTotals* __restrict__ tot, uint32_t lane)
 {
-    const uint32_t lane = threadIdx.x;
     const bool live = (int)lane < nf;
-    const uint32_t total = *toff_total;
     uint32_t P = 0, lo = 0;
     if (live) {
         const FrameDev& F = tab[lane];
@@ -755,6 +755,16 @@ __global__ __launch_bounds__(64) void k_setup_pairs(const FrameDev* __restrict__
         tot->wt = wt;
         tot->hist_len = 256u * wt;
     }
+    return make_uint2(my_len, my_base);
+}
+
+__global__ __launch_bounds__(64) void k_setup_pairs(const FrameDev* __restrict__ tab, int nf, uint32_t len_total,
+                                                    bool by_tiles, const uint32_t* __restrict__ toff,
+                                                    const uint32_t* __restrict__ toff_total, uint32_t capacity,
+                                                    uint32_t* __restrict__ counts, SortSeg* __restrict__ segs,
+                                                    SortTotals* __restrict__ tot)
+{
+    setup_pairs_wave(tab, nf, len_total, by_tiles, toff, *toff_total, capacity, counts, segs, tot, threadIdx.x);
 }
 
 // Tile id of the l-th tile of a footprint (row by row, left to right);
@@ -1234,6 +1244,77 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const FrameDev* __restrict_
         r.y = (t + 1 < T) ? pb + ts[t + 1] - ts[0] : pb + P;
     }
     ranges[F.t0 + t] = r;
+}
+
+// Calls of at most kFinishTiles tiles finish the counting binner's scalar
+// steps in one block of 1024 lanes instead of five launches: the exclusive
+// scan of the tile totals (in place, as the scan kernels leave it), the
+// arena hand-out of k_setup_pairs (by its first wave) and every tile's range
+// (as k_tile_ranges writes it, from the scanned totals and the frame's pair
+// count and first slot, which the first wave passes on through LDS).
+constexpr uint32_t kFinishThreads = 1024;
+constexpr uint32_t kFinishPerThread = 16;
+constexpr uint32_t kFinishTiles = kFinishThreads * kFinishPerThread;
+
+__global__ __launch_bounds__(kFinishThreads) void k_tiles_finish(const FrameDev* __restrict__ tab, int nf,
+                                                                 uint32_t ntiles, uint32_t capacity,
+                                                                 uint32_t* __restrict__ ttot,
+                                                                 uint32_t* __restrict__ counts,
+                                                                 SortSeg* __restrict__ segs,
+                                                                 SortTotals* __restrict__ tot,
+                                                                 uint2* __restrict__ ranges)
+{
+    __shared__ uint32_t s_wave[kFinishThreads / 64];
+    __shared__ uint32_t s_total;
+    __shared__ uint2 s_frame[SD7_MAX_FRAMES];  // (pairs, first slot) per frame
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // each lane's run of kFinishPerThread consecutive totals
+    const uint32_t i0 = tid * kFinishPerThread;
+    uint32_t v[kFinishPerThread], sum = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kFinishPerThread; ++k) {
+        v[k] = i0 + k < ntiles ? ttot[i0 + k] : 0u;
+        sum += v[k];
+    }
+    // exclusive prefix of the runs' sums: within the wave, then over waves
+    const uint32_t incl = wave_incl_scan(sum, lane);
+    if (lane == 63) s_wave[wave] = incl;
+    __syncthreads();
+    if (wave == 0) {
+        const uint32_t w = lane < kFinishThreads / 64 ? s_wave[lane] : 0u;
+        const uint32_t wi = wave_incl_scan(w, lane);
+        if (lane < kFinishThreads / 64) s_wave[lane] = wi - w;
+        if (lane == kFinishThreads / 64 - 1) s_total = wi;
+    }
+    __syncthreads();
+    uint32_t run = s_wave[wave] + incl - sum;
+#pragma unroll
+    for (uint32_t k = 0; k < kFinishPerThread; ++k) {
+        if (i0 + k < ntiles) ttot[i0 + k] = run;
+        run += v[k];
+    }
+    // the stores above are read back by the first wave (other lanes' runs)
+    __threadfence_block();
+    __syncthreads();
+    if (wave == 0) {
+        const uint2 fr = setup_pairs_wave(tab, nf, ntiles, true, ttot, s_total, capacity, counts, segs, tot, lane);
+        if ((int)lane < nf) s_frame[lane] = fr;
+    }
+    __syncthreads();
+    for (int f = 0; f < nf; ++f) {
+        const FrameDev& F = tab[f];
+        const uint32_t T = F.tiles_x * F.tiles_y;
+        const uint2 fr = s_frame[f];
+        const uint32_t* ts = ttot + F.t0;
+        for (uint32_t t = tid; t < T; t += kFinishThreads) {
+            uint2 r = make_uint2(0u, 0u);
+            if (fr.x > 0) {
+                r.x = fr.y + ts[t] - ts[0];
+                r.y = (t + 1 < T) ? fr.y + ts[t + 1] - ts[0] : fr.y + fr.x;
+            }
+            ranges[F.t0 + t] = r;
+        }
+    }
 }
 
 }  // namespace sd7
