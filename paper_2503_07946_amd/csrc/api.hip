@@ -68,7 +68,6 @@ struct Scratch {
     size_t sk_a, sv_a, sk_b;         // depth sort ping-pong (keys a, vals a, keys b)
     size_t pt_a, pt_b, pg_b;         // radix tile sort: tile keys and ping-pong buffers
     size_t toff;                     // tile offsets (scan of tiles per sorted Gaussian)
-    size_t dsort, dsort_words;       // small calls' depth sort: state cleared before each sort
     size_t dhist, dctr, dstat;       // its digit counts, tile counters, status words
     size_t srect;                    // footprints in depth order (counting binner)
     size_t sspan;                    // their tile-group spans (counting binner)
@@ -270,13 +269,12 @@ sd7_status make_plan(const sd7_frame* fr, int nf, int64_t cap, Plan& P, bool nee
     S.tot_pairs = take(sizeof(SortTotals));
     P.hist_entries = 256 * (size_t)std::max(P.onesweep ? 0u : P.max_wt_depth, P.counting ? 0u : P.max_wt_pairs);
     S.hist = take(4 * P.hist_entries);
-    // small calls' depth sort: digit counts [nf][4][256], tile counters [4]
-    // and status words [4][max_wt_depth][256], cleared together
-    S.dsort = off;
+    // small calls' depth sort: digit counts [nf][4][256] and tile counters [4]
+    // (zeroed by k_setup_depth), status words [4][max_wt_depth][256] (zeroed
+    // by k_depth_hist)
     S.dhist = take(P.onesweep ? 4 * 1024 * (size_t)nf : 0);
     S.dctr = take(P.onesweep ? 4 * 4 : 0);
     S.dstat = take(P.onesweep ? 4 * 4 * 256 * (size_t)P.max_wt_depth : 0);
-    S.dsort_words = (off - S.dsort) / 4;
     const size_t mat = P.counting ? P.matrix_entries : 0;
     P.cnt = take(4 * mat);
     P.ttot = take(4 * (P.counting ? T + 4 : 0));
@@ -586,7 +584,12 @@ sd7_status do_bin(const Call& c)
     SortTotals* tot_kept = c.at<SortTotals>(S.tot_kept);
     SortTotals* tot_pairs = c.at<SortTotals>(S.tot_pairs);
     uint32_t* words = c.at<uint32_t>(S.words);
-    k_setup_depth<<<1, 64, 0, c.st>>>(c.tab, nf, c.counts, segs_all, tot_all, segs_kept, tot_kept);
+    // the one-launch-per-digit sort's digit counts and tile counters start at
+    // zero (its status words are zeroed by k_depth_hist)
+    const bool os = c.P.onesweep && c.P.max_wt_depth;
+    k_setup_depth<<<1, 256, 0, c.st>>>(c.tab, nf, c.counts, segs_all, tot_all, segs_kept, tot_kept,
+                                       os ? c.at<uint32_t>(S.dhist) : nullptr,
+                                       os ? (uint32_t)((S.dstat - S.dhist) / 4) : 0u);
     LAUNCH_CHECK("k_setup_depth");
     // depth sort: key_depth -> (a) -> (b) -> (a) -> (b = order)
     uint32_t* ka = c.at<uint32_t>(S.sk_a);
@@ -600,8 +603,7 @@ sd7_status do_bin(const Call& c)
         uint32_t* ctr = c.at<uint32_t>(S.dctr);
         uint32_t* stat = c.at<uint32_t>(S.dstat);
         const size_t sw = 256 * (size_t)mw;  // status words of one pass
-        if ((s = fill(c, c.at<uint32_t>(S.dsort), S.dsort_words, 0)) != SD7_OK) return s;
-        k_depth_hist<<<mw, 256, 0, c.st>>>(dkey, segs_all, nf, tot_all, dh);
+        k_depth_hist<<<mw, 256, 0, c.st>>>(dkey, segs_all, nf, tot_all, dh, stat, sw);
         LAUNCH_CHECK("k_depth_hist");
         k_depth_pass<true, true><<<mw, 256, 0, c.st>>>(dkey, nullptr, ka, va, segs_all, nf, tot_all, 0, dh, stat,
                                                        ctr, c.counts);

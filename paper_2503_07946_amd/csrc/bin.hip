@@ -347,13 +347,18 @@ constexpr uint32_t kLookbackSpins = 1u << 22;  // polls of an unpublished tile b
 constexpr int kLookWindow = 16;                 // earlier tiles a look-back step reads at once
 
 // Per frame, the kept keys of every value of every digit: dh[f][digit][256].
+// The block that counts work tile w also zeroes the tile's status words of
+// the four passes (stat + p * sw + 256 w), which the passes then publish in.
 __global__ __launch_bounds__(256) void k_depth_hist(const uint32_t* __restrict__ keys,
                                                     const SortSeg* __restrict__ segs, int nseg,
-                                                    const SortTotals* __restrict__ tot, uint32_t* __restrict__ dh)
+                                                    const SortTotals* __restrict__ tot, uint32_t* __restrict__ dh,
+                                                    uint32_t* __restrict__ stat, size_t sw)
 {
     __shared__ uint32_t h[4][256];
     const uint32_t nwt = tot->wt;
     for (uint32_t w = blockIdx.x; w < nwt; w += gridDim.x) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) stat[p * sw + (size_t)w * 256 + threadIdx.x] = 0;
         const int s = seg_of_tile(segs, nseg, w);
         const SortSeg sg = segs[s];
         h[0][threadIdx.x] = 0; h[1][threadIdx.x] = 0; h[2][threadIdx.x] = 0; h[3][threadIdx.x] = 0;
@@ -583,11 +588,16 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t lane)
     return v;
 }
 
-__global__ __launch_bounds__(64) void k_setup_depth(const FrameDev* __restrict__ tab, int nf,
-                                                    const uint32_t* __restrict__ counts,
-                                                    SortSeg* __restrict__ segs_all, SortTotals* __restrict__ tot_all,
-                                                    SortSeg* __restrict__ segs_kept, SortTotals* __restrict__ tot_kept)
+// Also zeroes `clear` (clear_words words: the small call's digit counts and
+// tile counters) with all 256 lanes; the first wave sets up the segments.
+__global__ __launch_bounds__(256) void k_setup_depth(const FrameDev* __restrict__ tab, int nf,
+                                                     const uint32_t* __restrict__ counts,
+                                                     SortSeg* __restrict__ segs_all, SortTotals* __restrict__ tot_all,
+                                                     SortSeg* __restrict__ segs_kept, SortTotals* __restrict__ tot_kept,
+                                                     uint32_t* __restrict__ clear, uint32_t clear_words)
 {
+    for (uint32_t i = threadIdx.x; i < clear_words; i += blockDim.x) clear[i] = 0;
+    if (threadIdx.x >= 64) return;
     const uint32_t lane = threadIdx.x;
     const bool live = (int)lane < nf;
     const uint32_t n = live ? tab[lane].n : 0u, g0 = live ? tab[lane].g0 : 0u;
