@@ -47,8 +47,8 @@ FP32_NONPACKED_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 RASTER_OPS_PER_TEST = 12
 RASTER_OPS_PER_CONTRIBUTION = 12
 RASTER_SRC_DIR = "paper_2503_07946_amd/csrc"
-RASTER_SRC_SHA256 = "8186d670ba0e1d3fe6bd5f30342a62681aea63c89381758ba9f7cc2a80779d45"
-RASTER_TRAFFIC_BYTES = 2388686848       # (1010101 KiB x 2 + 312500 KiB) x 1024
+RASTER_SRC_SHA256 = "9b67b0183a765c4306ba94e8a59dd670e20812a8393c57d73426d64e622c401d"
+RASTER_TRAFFIC_BYTES = 2387521536       # (1009532 KiB x 2 + 312500 KiB) x 1024
 RASTER_VALU_INSTRUCTIONS = 1108568418   # SQ_INSTS_VALU per launch (wave64 instructions)
 
 
