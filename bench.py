@@ -47,9 +47,9 @@ FP32_NONPACKED_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 RASTER_OPS_PER_TEST = 12
 RASTER_OPS_PER_CONTRIBUTION = 12
 RASTER_SRC_DIR = "paper_2503_07946_amd/csrc"
-RASTER_SRC_SHA256 = "9b67b0183a765c4306ba94e8a59dd670e20812a8393c57d73426d64e622c401d"
-RASTER_TRAFFIC_BYTES = 2387521536       # (1009532 KiB x 2 + 312500 KiB) x 1024
-RASTER_VALU_INSTRUCTIONS = 1108568418   # SQ_INSTS_VALU per launch (wave64 instructions)
+RASTER_SRC_SHA256 = "757a67e55a240551d2becfc5b844bd2ee10e4c6950d2f6909d51674fd5711539"
+RASTER_TRAFFIC_BYTES = 2399395840       # (1015330 KiB x 2 + 312500 KiB) x 1024
+RASTER_VALU_INSTRUCTIONS = 1040066229   # SQ_INSTS_VALU per launch (wave64 instructions)
 
 
 def raster_src_digest() -> str:

@@ -104,6 +104,7 @@ struct Plan {
 };
 
 constexpr uint32_t kOneSweepTiles = 512;
+constexpr uint32_t kRasterMaskedTiles = 4096;  // tiles of a call above which the compositing masks its blends
 constexpr uint32_t kScanSplitTiles = 16384;  // tiles of a call up to which the column scan splits its chunks  // depth-sort work tiles up to which a call sorts one launch per digit
 constexpr uint64_t kBinWaves = 131072; // (chunk, group) waves the counting binner aims for per call
 constexpr uint64_t kMaxChunks = 512;   // chunks per frame (the depth of the per-tile column scan)
@@ -723,14 +724,22 @@ sd7_status do_raster(const Call& c)
     const float4* sp = c.at<float4>(L.off_splat);
     // 64-bit addressing where a frame's splat records span 4 GiB or more
     const bool wide = c.P.max_n > (int64_t)(UINT32_MAX / (4 * kSplatFloats));
-    if (c.count && wide)
-        k_raster<true, true><<<c.P.tblocks, 64, 0, c.st>>>(c.tab, c.P.tmap, rg, pg, sp);
-    else if (c.count)
-        k_raster<true, false><<<c.P.tblocks, 64, 0, c.st>>>(c.tab, c.P.tmap, rg, pg, sp);
-    else if (wide)
-        k_raster<false, true><<<c.P.tblocks, 64, 0, c.st>>>(c.tab, c.P.tmap, rg, pg, sp);
-    else
-        k_raster<false, false><<<c.P.tblocks, 64, 0, c.st>>>(c.tab, c.P.tmap, rg, pg, sp);
+    // masked blends where several tile waves share each SIMD
+    const bool masked = c.P.tblocks > kRasterMaskedTiles;
+    auto launch = [&](auto count, auto wide_c, auto masked_c) {
+        k_raster<decltype(count)::value, decltype(wide_c)::value, decltype(masked_c)::value>
+            <<<c.P.tblocks, 64, 0, c.st>>>(c.tab, c.P.tmap, rg, pg, sp);
+    };
+    auto with_masked = [&](auto count, auto wide_c) {
+        if (masked) launch(count, wide_c, std::true_type{});
+        else launch(count, wide_c, std::false_type{});
+    };
+    auto with_wide = [&](auto count) {
+        if (wide) with_masked(count, std::true_type{});
+        else with_masked(count, std::false_type{});
+    };
+    if (c.count) with_wide(std::true_type{});
+    else with_wide(std::false_type{});
     LAUNCH_CHECK("k_raster");
     return SD7_OK;
 }

@@ -69,7 +69,13 @@ __device__ __forceinline__ void splat_exponents(const Splat& s, float fx, float 
 // List entries whose records one scalar-load batch brings in.
 constexpr uint32_t kRasterBatch = 2;
 
-template <bool COUNT, bool WIDE>
+// MASKED: a band's blend runs under an execution mask of the lanes the splat
+// reaches (fewer vector instructions per entry, more scalar ones: faster
+// where many waves share each SIMD); otherwise every lane of a band that some
+// lane passes blends, with alpha 0 where it does not (fewer instructions on
+// one wave's own chain: faster for calls of few tiles, where a tile's wave
+// runs nearly alone).  Both give the same bits.
+template <bool COUNT, bool WIDE, bool MASKED>
 __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab, BlockMap bm,
                                                const uint2* __restrict__ ranges,
                                                const uint32_t* __restrict__ pair_g,
@@ -107,27 +113,33 @@ __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab,
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const bool pass = p[k] >= th[k];
-            if (__ballot(pass) == 0) continue;  // the splat reaches no pixel of band k
-            const float alpha = pass ? fminf(kAlphaMax, exp2_fast(p[k])) : 0.0f;
-            const float w = T[k] * alpha;
-            T[k] = fmaf(-T[k], alpha, T[k]);
-            C0[k] = fmaf(s.r, w, C0[k]);
-            C1[k] = fmaf(s.g, w, C1[k]);
-            C2[k] = fmaf(s.b, w, C2[k]);
-            if (COUNT) ncon[k] += pass ? 1u : 0u;
             // Only a passing pixel can stop (T >= 1e-4 before).  Once per
             // pixel: take this splat's blend back (T to at least 1e-4, so
             // the pixel cannot stop again) and retire the pixel, which has
             // consumed the entries before e.
-            const bool stop = T[k] < kTMin;
-            if (__ballot(stop)) {
-                T[k] = stop ? fmaxf(T[k] + w, kTMin) : T[k];
-                C0[k] = stop ? fmaf(-s.r, w, C0[k]) : C0[k];
-                C1[k] = stop ? fmaf(-s.g, w, C1[k]) : C1[k];
-                C2[k] = stop ? fmaf(-s.b, w, C2[k]) : C2[k];
-                if (COUNT) ncon[k] -= stop ? 1u : 0u;
-                th[k] = stop ? kFar : th[k];
-                last[k] = stop ? e - rg.x : last[k];
+            auto band = [&](float alpha) {
+                const float w = T[k] * alpha;
+                T[k] = fmaf(-T[k], alpha, T[k]);
+                C0[k] = fmaf(s.r, w, C0[k]);
+                C1[k] = fmaf(s.g, w, C1[k]);
+                C2[k] = fmaf(s.b, w, C2[k]);
+                if (COUNT) ncon[k] += pass ? 1u : 0u;
+                const bool stop = T[k] < kTMin;
+                if (__ballot(stop)) {
+                    T[k] = stop ? fmaxf(T[k] + w, kTMin) : T[k];
+                    C0[k] = stop ? fmaf(-s.r, w, C0[k]) : C0[k];
+                    C1[k] = stop ? fmaf(-s.g, w, C1[k]) : C1[k];
+                    C2[k] = stop ? fmaf(-s.b, w, C2[k]) : C2[k];
+                    if (COUNT) ncon[k] -= stop ? 1u : 0u;
+                    th[k] = stop ? kFar : th[k];
+                    last[k] = stop ? e - rg.x : last[k];
+                }
+            };
+            if constexpr (MASKED) {
+                if (pass) band(fminf(kAlphaMax, exp2_fast(p[k])));  // skipped when no lane passes
+            } else {
+                if (__ballot(pass) == 0) continue;  // the splat reaches no pixel of band k
+                band(pass ? fminf(kAlphaMax, exp2_fast(p[k])) : 0.0f);
             }
         }
     };
