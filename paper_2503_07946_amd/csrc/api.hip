@@ -83,6 +83,7 @@ struct Plan {
     size_t hist_entries, partial_entries;
     BlockMap gmap;   // blocks of 256 Gaussians per frame
     SceneGroups sgrp;  // frames sharing a scene; blocks of 256 Gaussians per group
+    bool single_runs;  // every scene group has one frame
     uint32_t sblocks;
     BlockMap tmap;   // one block per tile
     uint32_t gblocks, tblocks;
@@ -207,6 +208,7 @@ sd7_status make_plan(const sd7_frame* fr, int nf, int64_t cap, Plan& P, bool nee
         P.sgrp.first[ng] = (uint8_t)q;
         P.sgrp.start[ng] = (uint32_t)std::min<uint64_t>(units, UINT32_MAX);
         P.sgrp.ng = ng;
+        P.single_runs = ng == nf;
         // whole rounds of resident blocks, equal shares of the units
         const uint64_t rounds = std::max<uint64_t>(1, units / ((uint64_t)kSliceResident * kSliceUnitsPerBlock));
         P.sblocks = (uint32_t)std::min<uint64_t>(units, kSliceResident * rounds);
@@ -565,9 +567,13 @@ sd7_status do_slice_project(const Call& c)
     }
     sd7_status s = fill(c, c.counts, (size_t)SD7_CNT_WORDS * L.nframes, 0);
     if (s != SD7_OK || c.P.sblocks == 0) return s;
-    k_slice_project<<<c.P.sblocks, kBlock, 0, c.st>>>(
-        c.tab, c.P.sgrp, c.at<float>(L.off_mu_c), c.at<float>(L.off_cov_c), c.at<float>(L.off_alpha_c),
-        c.at<float4>(L.off_splat), c.at<uint4>(L.off_rect), c.at<uint32_t>(L.off_depth_key), c.counts);
+    auto launch = [&](auto block_kept) {
+        k_slice_project<decltype(block_kept)::value><<<c.P.sblocks, kBlock, 0, c.st>>>(
+            c.tab, c.P.sgrp, c.at<float>(L.off_mu_c), c.at<float>(L.off_cov_c), c.at<float>(L.off_alpha_c),
+            c.at<float4>(L.off_splat), c.at<uint4>(L.off_rect), c.at<uint32_t>(L.off_depth_key), c.counts);
+    };
+    if (c.P.single_runs) launch(std::true_type{});
+    else launch(std::false_type{});
     LAUNCH_CHECK("k_slice_project");
     return SD7_OK;
 }

@@ -460,15 +460,26 @@ __global__ __launch_bounds__(kBlock) void k_slice_bwd(const FrameDev* __restrict
     } else {
         gl_t = gl_d = 0.0;
     }
-    if (F.g_lambda) {  // one atomic per wave and value
+    if (F.g_lambda) {  // uniform over the block (one frame)
+        // wave sums, the block's sum of them in LDS, then one atomic per
+        // block and value: same-address atomics serialize in L2, and one
+        // per wave and value made up most of this kernel's time
+        __shared__ double s_gl[kBlock / 64][2];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
             gl_t += __shfl_xor(gl_t, off);
             gl_d += __shfl_xor(gl_d, off);
         }
         if (__lane_id() == 0) {
-            atomicAdd(&F.g_lambda[0], (float)gl_t);
-            atomicAdd(&F.g_lambda[1], (float)gl_d);
+            s_gl[threadIdx.x / 64][0] = gl_t;
+            s_gl[threadIdx.x / 64][1] = gl_d;
+        }
+        __syncthreads();
+        if (threadIdx.x < 2) {
+            double sum = 0.0;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) sum += s_gl[w][threadIdx.x];
+            atomicAdd(&F.g_lambda[threadIdx.x], (float)sum);
         }
     }
 }

@@ -25,6 +25,15 @@ struct ShLds {
     __device__ __forceinline__ float operator()(int j, uint32_t) const { return s[j * kBlock + threadIdx.x]; }
 };
 
+// Kept counts: with BLOCK_KEPT (calls whose scene groups have one frame each,
+// so every run is one frame) the block sums its waves' counts in LDS and adds
+// them to the frame's counter with one atomic per run; same-address atomics
+// serialize in L2, and one per wave made up about half of a one-frame call
+// (3,125 waves on one counter).  Runs of several frames keep one atomic per
+// wave and frame: there each counter's atomics spread over the frames of the
+// run and the launch, and the barriers of the block sums cost more (12 % at
+// 25 frames of 200k Gaussians).
+template <bool BLOCK_KEPT>
 __global__ __launch_bounds__(kBlock, 3) void k_slice_project(const FrameDev* __restrict__ tab, SceneGroups sg,
                                                           float* __restrict__ mu_c, float* __restrict__ cov_c,
                                                           float* __restrict__ alpha_c, float4* __restrict__ splat,
@@ -41,6 +50,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_slice_project(const FrameDev* __r
     const bool rev = lb & 1u;
     int gi = group_of_unit(sg, rev ? hi - 1u : lo);
     __shared__ float s_sh[48 * kBlock];
+    __shared__ uint32_t s_kept[SD7_MAX_FRAMES];  // kept Gaussians of the block per frame of the run
     while (lo < hi) {  // one run: a Gaussian block and consecutive frames of its group
         uint32_t ua, ub;  // the run's units [ua, ub)
         uint32_t nq, gb;
@@ -63,6 +73,12 @@ __global__ __launch_bounds__(kBlock, 3) void k_slice_project(const FrameDev* __r
         const uint32_t n = F0.n;
         const uint32_t qa = ua - sg.start[gi] - gb * nq;
         const uint32_t run = ub - ua;
+        // thread t < run zeroes, and after the frames adds out, the count of
+        // the run's frame t (the previous run's reads were its own)
+        if constexpr (BLOCK_KEPT) {
+            if (threadIdx.x < run) s_kept[threadIdx.x] = 0;
+            __syncthreads();
+        }
         const uint32_t i = gb * kBlock + threadIdx.x;
         const bool valid = i < n;
         SliceFixed S;
@@ -115,7 +131,18 @@ __global__ __launch_bounds__(kBlock, 3) void k_slice_project(const FrameDev* __r
                 keep = project_emit(F, i, ac, mc, cv, ShLds{s_sh}, splat, rect, depth_key);
             }
             wave_flags(flag, counts, f);
-            wave_kept(keep, counts, f);
+            if constexpr (BLOCK_KEPT) {
+                wave_kept(keep, &s_kept[q - qb]);
+            } else {
+                const uint64_t kept = __ballot(keep);
+                if (__lane_id() == 0 && kept)
+                    atomicAdd(&counts[f * SD7_CNT_WORDS + SD7_CNT_KEPT], (uint32_t)__popcll(kept));
+            }
+        }
+        if constexpr (BLOCK_KEPT) {
+            __syncthreads();
+            if (threadIdx.x < run && s_kept[threadIdx.x])
+                atomicAdd(&counts[sg.frame[qb + threadIdx.x] * SD7_CNT_WORDS + SD7_CNT_KEPT], s_kept[threadIdx.x]);
         }
     }
 }
