@@ -106,21 +106,25 @@ struct Plan {
 
 constexpr uint32_t kOneSweepTiles = 512;
 constexpr uint32_t kRasterMaskedTiles = 4096;  // tiles of a call above which the compositing masks its blends
+constexpr uint32_t kRasterBandTiles = 256;     // tiles of a call up to which each band gets a wave
 constexpr uint32_t kScanSplitTiles = 16384;  // tiles of a call up to which the column scan splits its chunks  // depth-sort work tiles up to which a call sorts one launch per digit
 constexpr uint64_t kBinWaves = 131072; // (chunk, group) waves the counting binner aims for per call
 constexpr uint64_t kMaxChunks = 512;   // chunks per frame (the depth of the per-tile column scan)
 constexpr size_t kMaxMatrix = (size_t)1 << 28;  // count-matrix entries of one call
 
 // Binning chunks per frame: enough (chunk, group) waves over the call to fill
-// the chip, at most kMaxChunks, and no more than one per 256 Gaussians.  The
-// kernels cut the kept Gaussians (a count known on the device) into this many
-// chunks.
-uint32_t chunk_count(int64_t n, uint32_t groups, int nf)
+// the chip, at most kMaxChunks, and no more than one per 256 Gaussians (per 64
+// in frames of at most 256 tiles, where a chunk's row of the count matrix
+// costs little and a few long chunks would leave the placement waves walking
+// their entries one after another).  The kernels cut the kept Gaussians (a
+// count known on the device) into this many chunks.
+uint32_t chunk_count(int64_t n, uint32_t groups, uint32_t tiles, int nf)
 {
     if (n <= 0) return 0;
     const uint64_t per = (uint64_t)nf * groups;
     uint64_t nch = std::min<uint64_t>(std::max<uint64_t>(1, (kBinWaves + per - 1) / per), kMaxChunks);
-    return (uint32_t)std::min<uint64_t>(nch, ((uint64_t)n + 255) / 256);
+    const uint64_t least = tiles <= 256 ? 64 : 256;
+    return (uint32_t)std::min<uint64_t>(nch, ((uint64_t)n + least - 1) / least);
 }
 
 sd7_status make_plan(const sd7_frame* fr, int nf, int64_t cap, Plan& P, bool need_bwd)
@@ -164,7 +168,7 @@ sd7_status make_plan(const sd7_frame* fr, int nf, int64_t cap, Plan& P, bool nee
         P.max_n = std::max(P.max_n, n);
         wt_depth += ceil_div(n, kSortItems);
         const uint32_t groups = ceil_div(tx, kGroup) * ceil_div(ty, kGroup);
-        P.nch[f] = chunk_count(n, groups, nf);
+        P.nch[f] = chunk_count(n, groups, tx * ty, nf);
         P.m0[f] = (uint32_t)std::min<size_t>(P.matrix_entries, UINT32_MAX);
         P.cmap.start[f] = P.cblocks;
         P.kmap.start[f] = P.kblocks;
@@ -591,21 +595,31 @@ sd7_status do_bin(const Call& c)
     SortTotals* tot_kept = c.at<SortTotals>(S.tot_kept);
     SortTotals* tot_pairs = c.at<SortTotals>(S.tot_pairs);
     uint32_t* words = c.at<uint32_t>(S.words);
-    // the one-launch-per-digit sort's digit counts and tile counters start at
-    // zero (its status words are zeroed by k_depth_hist)
-    const bool os = c.P.onesweep && c.P.max_wt_depth;
-    k_setup_depth<<<1, 256, 0, c.st>>>(c.tab, nf, c.counts, segs_all, tot_all, segs_kept, tot_kept,
-                                       os ? c.at<uint32_t>(S.dhist) : nullptr,
-                                       os ? (uint32_t)((S.dstat - S.dhist) / 4) : 0u);
-    LAUNCH_CHECK("k_setup_depth");
-    // depth sort: key_depth -> (a) -> (b) -> (a) -> (b = order)
+    // Depth sort: one block per frame where every frame's keys fit one block;
+    // otherwise the segments, then four digit passes.  The one-launch-per-digit
+    // sort's digit counts and tile counters start at zero (its status words
+    // are zeroed by k_depth_hist).
+    uint32_t* order = c.at<uint32_t>(L.off_order);
+    const uint32_t* dkey = c.at<uint32_t>(L.off_depth_key);
+    const bool small = c.P.max_n <= (int64_t)kSmallSortItems;
+    const bool os = !small && c.P.onesweep && c.P.max_wt_depth;
+    if (small) {
+        k_depth_small<<<nf, kSmallSortThreads, 0, c.st>>>(c.tab, c.counts, dkey, order);
+        LAUNCH_CHECK("k_depth_small");
+    } else {
+        k_setup_depth<<<1, 256, 0, c.st>>>(c.tab, nf, c.counts, segs_all, tot_all, segs_kept, tot_kept,
+                                           os ? c.at<uint32_t>(S.dhist) : nullptr,
+                                           os ? (uint32_t)((S.dstat - S.dhist) / 4) : 0u);
+        LAUNCH_CHECK("k_setup_depth");
+    }
+    // digit passes: key_depth -> (a) -> (b) -> (a) -> (b = order)
     uint32_t* ka = c.at<uint32_t>(S.sk_a);
     uint32_t* va = c.at<uint32_t>(S.sv_a);
     uint32_t* kb = c.at<uint32_t>(S.sk_b);
-    uint32_t* order = c.at<uint32_t>(L.off_order);
-    const uint32_t* dkey = c.at<uint32_t>(L.off_depth_key);
     const uint32_t mw = c.P.max_wt_depth;
-    if (c.P.onesweep && mw) {
+    if (small) {
+        // sorted above
+    } else if (os) {
         uint32_t* dh = c.at<uint32_t>(S.dhist);
         uint32_t* ctr = c.at<uint32_t>(S.dctr);
         uint32_t* stat = c.at<uint32_t>(S.dstat);
@@ -730,6 +744,14 @@ sd7_status do_raster(const Call& c)
     const float4* sp = c.at<float4>(L.off_splat);
     // 64-bit addressing where a frame's splat records span 4 GiB or more
     const bool wide = c.P.max_n > (int64_t)(UINT32_MAX / (4 * kSplatFloats));
+    if (!c.count && c.P.tblocks <= kRasterBandTiles) {  // one wave per band of each tile
+        if (wide)
+            k_raster_bands<true><<<4 * c.P.tblocks, 64, 0, c.st>>>(c.tab, c.P.tmap, rg, pg, sp);
+        else
+            k_raster_bands<false><<<4 * c.P.tblocks, 64, 0, c.st>>>(c.tab, c.P.tmap, rg, pg, sp);
+        LAUNCH_CHECK("k_raster_bands");
+        return SD7_OK;
+    }
     // masked blends where several tile waves share each SIMD
     const bool masked = c.P.tblocks > kRasterMaskedTiles;
     auto launch = [&](auto count, auto wide_c, auto masked_c) {

@@ -588,6 +588,46 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t lane)
     return v;
 }
 
+// Depth order of calls whose frames hold at most kSmallSortItems Gaussians
+// each: one block per frame sorts (depth key, index) pairs in LDS with a
+// bitonic network and writes the kept Gaussians' indices in that order (the
+// order the radix passes give: depth, then index; culled keys, all ones, sort
+// last).  One launch in place of the setup, the digit count and four digit
+// passes, which a call of a thousand Gaussians spends most of its time
+// launching.
+constexpr uint32_t kSmallSortItems = 2048;
+constexpr uint32_t kSmallSortThreads = kSmallSortItems / 2;  // one compare-exchange per thread and step
+
+__global__ __launch_bounds__(kSmallSortThreads) void k_depth_small(const FrameDev* __restrict__ tab,
+                                                                   const uint32_t* __restrict__ counts,
+                                                                   const uint32_t* __restrict__ dkey,
+                                                                   uint32_t* __restrict__ order)
+{
+    __shared__ uint64_t s_k[kSmallSortItems];
+    const FrameDev& F = tab[blockIdx.x];
+    const uint32_t n = F.n, tid = threadIdx.x;
+    uint32_t m = 64;  // a power of two >= n (all threads take part in every step)
+    while (m < n) m <<= 1;
+    for (uint32_t i = tid; i < m; i += kSmallSortThreads)
+        s_k[i] = i < n ? (uint64_t)dkey[F.g0 + i] << 32 | i : ~0ull;
+    __syncthreads();
+    for (uint32_t k = 2; k <= m; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t i = 2 * tid - (tid & (j - 1));  // the pair (i, i + j), i's bit j clear
+            if (i + j < m) {
+                const uint64_t a = s_k[i], b = s_k[i + j];
+                if ((a > b) == ((i & k) == 0)) {  // ascending where bit k of i is clear
+                    s_k[i] = b;
+                    s_k[i + j] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const uint32_t kept = counts[blockIdx.x * SD7_CNT_WORDS + SD7_CNT_KEPT];
+    for (uint32_t i = tid; i < kept; i += kSmallSortThreads) order[F.g0 + i] = (uint32_t)s_k[i];
+}
+
 // Also zeroes `clear` (clear_words words: the small call's digit counts and
 // tile counters) with all 256 lanes; the first wave sets up the segments.
 __global__ __launch_bounds__(256) void k_setup_depth(const FrameDev* __restrict__ tab, int nf,

@@ -75,15 +75,20 @@ constexpr uint32_t kRasterBatch = 2;
 // lane passes blends, with alpha 0 where it does not (fewer instructions on
 // one wave's own chain: faster for calls of few tiles, where a tile's wave
 // runs nearly alone).  Both give the same bits.
-template <bool COUNT, bool WIDE, bool MASKED>
-__global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab, BlockMap bm,
-                                               const uint2* __restrict__ ranges,
-                                               const uint32_t* __restrict__ pair_g,
-                                               const float4* __restrict__ splat)
+//
+// The work of one wave: tile gt of the call (block gt of the one-block-per-tile
+// map), bands K0 .. K1 - 1 of each lane (all four, or one band per wave where
+// a call has so few tiles that their lists would otherwise be walked by a few
+// waves alone).  A pixel's arithmetic is the same whichever wave blends it.
+template <bool COUNT, bool WIDE, bool MASKED, int K0, int K1>
+__device__ __forceinline__ void raster_tile(const FrameDev* __restrict__ tab, const BlockMap& bm, uint32_t gt,
+                                            const uint2* __restrict__ ranges, const uint32_t* __restrict__ pair_g,
+                                            const float4* __restrict__ splat)
 {
-    const int f = frame_of_block(bm, blockIdx.x);
+    static_assert(0 <= K0 && K0 < K1 && K1 <= 4, "bands of a lane");
+    const int f = frame_of_block(bm, gt);
     const FrameDev& F = tab[f];
-    const uint32_t tile = blockIdx.x - bm.start[f];
+    const uint32_t tile = gt - bm.start[f];
     const uint32_t tx = tile % F.tiles_x, ty = tile / F.tiles_x;
     const uint32_t lane = threadIdx.x;
     const uint32_t px = tx * kTile + (lane & 15);
@@ -95,7 +100,7 @@ __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab,
     float th[4], T[4], C0[4], C1[4], C2[4];
     uint32_t last[4], ncon[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = K0; k < K1; ++k) {
         const uint32_t py = py0 + 4 * k;
         th[k] = (px < F.W && py < F.H) ? kLog2AlphaMin : kFar;
         T[k] = 1.0f;
@@ -106,12 +111,12 @@ __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab,
     const uint2 rg = ranges[F.t0 + tile];
     const float4* __restrict__ rec = splat + (size_t)F.g0 * 3;
     const uint32_t gmax = __builtin_amdgcn_readfirstlane(F.n - 1);  // pairs exist only if n > 0
-    // Blend one splat (list entry e) into the lane's four pixels.
+    // Blend one splat (list entry e) into the lane's pixels of bands K0 .. K1 - 1.
     auto blend = [&](const Splat& s, uint32_t e) {
         float dx, Bdx, dy0, p[4];
         splat_exponents(s, fx, fy0, dx, Bdx, dy0, p);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = K0; k < K1; ++k) {
             const bool pass = p[k] >= th[k];
             // Only a passing pixel can stop (T >= 1e-4 before).  Once per
             // pixel: take this splat's blend back (T to at least 1e-4, so
@@ -188,7 +193,10 @@ __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab,
         using Full = std::false_type;
         using Guarded = std::true_type;
         auto all_stopped = [&]() {
-            return __ballot(fminf(fminf(th[0], th[1]), fminf(th[2], th[3])) < kFar) == 0;
+            float m = th[K0];
+#pragma unroll
+            for (int k = K0 + 1; k < K1; ++k) m = fminf(m, th[k]);
+            return __ballot(m < kFar) == 0;
         };
 #pragma unroll
         for (uint32_t j = 0; j < NB; ++j) ia[j] = idx(j);
@@ -216,7 +224,7 @@ __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab,
     }
     const size_t plane = (size_t)F.W * F.H;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = K0; k < K1; ++k) {
         const uint32_t py = py0 + 4 * k;
         if (px < F.W && py < F.H) {
             const size_t pix = (size_t)py * F.W + px;
@@ -227,6 +235,33 @@ __global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab,
             F.last[pix] = th[k] < kFar ? rg.y - rg.x : last[k];  // a pixel that never stopped used all
             if (COUNT && F.ncontrib) F.ncontrib[pix] = ncon[k];
         }
+    }
+}
+
+template <bool COUNT, bool WIDE, bool MASKED>
+__global__ __launch_bounds__(64) void k_raster(const FrameDev* __restrict__ tab, BlockMap bm,
+                                               const uint2* __restrict__ ranges,
+                                               const uint32_t* __restrict__ pair_g,
+                                               const float4* __restrict__ splat)
+{
+    raster_tile<COUNT, WIDE, MASKED, 0, 4>(tab, bm, blockIdx.x, ranges, pair_g, splat);
+}
+
+// Calls of at most a few hundred tiles: wave 4 t + k takes band k of tile t,
+// so each list is walked by four waves with a quarter of the vector work each
+// (a call of 16 tiles would otherwise run 16 waves on a chip of 1,024 SIMDs).
+template <bool WIDE>
+__global__ __launch_bounds__(64) void k_raster_bands(const FrameDev* __restrict__ tab, BlockMap bm,
+                                                     const uint2* __restrict__ ranges,
+                                                     const uint32_t* __restrict__ pair_g,
+                                                     const float4* __restrict__ splat)
+{
+    const uint32_t gt = blockIdx.x >> 2;
+    switch (blockIdx.x & 3u) {
+    case 0: raster_tile<false, WIDE, false, 0, 1>(tab, bm, gt, ranges, pair_g, splat); break;
+    case 1: raster_tile<false, WIDE, false, 1, 2>(tab, bm, gt, ranges, pair_g, splat); break;
+    case 2: raster_tile<false, WIDE, false, 2, 3>(tab, bm, gt, ranges, pair_g, splat); break;
+    default: raster_tile<false, WIDE, false, 3, 4>(tab, bm, gt, ranges, pair_g, splat); break;
     }
 }
 
