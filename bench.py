@@ -47,8 +47,8 @@ FP32_NONPACKED_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 RASTER_OPS_PER_TEST = 12
 RASTER_OPS_PER_CONTRIBUTION = 12
 RASTER_SRC_DIR = "paper_2503_07946_amd/csrc"
-RASTER_SRC_SHA256 = "e0ba95c942f317dd67773fcab883f8831aebf06247a25a999a2303a3440c3c60"
-RASTER_TRAFFIC_BYTES = 2398978048       # (1015126 KiB x 2 + 312500 KiB) x 1024
+RASTER_SRC_SHA256 = "289ae38be2ab3ce0cd9b13878f1b4f351d350560c7ad0e128520ee2a7b567e3f"
+RASTER_TRAFFIC_BYTES = 2398679040       # (1014980 KiB x 2 + 312500 KiB) x 1024
 RASTER_VALU_INSTRUCTIONS = 1040066229   # SQ_INSTS_VALU per launch (wave64 instructions)
 
 
